@@ -1,0 +1,489 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: brute-force
+algebra, closed forms printed in the paper (Propositions 2, 6, 7, Lemma 4,
+Theorem 5), special cases that reduce to library routines (scipy's Sylvester
+Hadamard matrix, numpy's Philox generator, numpy's median, torch's bfloat16 and
+float8_e4m3fn casts), and invariants that a dropped term, a wrong sign or a
+transposed operand would break.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+from paper_2105_05879_amd import workloads
+
+
+# ---------------------------------------------------------------- helpers ---
+
+def gf2_rank(rows):
+    """Rank over F_2 of a matrix given as a list of integer row bitmasks."""
+    rows = list(rows)
+    rank = 0
+    for bit in range(64):
+        piv = next((r for r in range(rank, len(rows)) if (rows[r] >> bit) & 1), None)
+        if piv is None:
+            continue
+        rows[rank], rows[piv] = rows[piv], rows[rank]
+        for r in range(len(rows)):
+            if r != rank and (rows[r] >> bit) & 1:
+                rows[r] ^= rows[rank]
+        rank += 1
+    return rank
+
+
+def gf2_rank_batch(R):
+    """Vectorised F_2 rank of many k x k matrices, R: (P, k) uint64 row masks."""
+    R = R.copy()
+    P, k = R.shape
+    rank = np.zeros(P, dtype=np.int64)
+    used = np.zeros((P, k), dtype=bool)
+    for bit in range(k):
+        has = ((R >> np.uint64(bit)) & np.uint64(1)).astype(bool) & ~used
+        piv_exists = has.any(axis=1)
+        piv = np.argmax(has, axis=1)
+        prow = R[np.arange(P), piv]
+        clear = ((R >> np.uint64(bit)) & np.uint64(1)).astype(bool)
+        clear[np.arange(P), piv] = False
+        clear &= piv_exists[:, None]
+        R = np.where(clear, R ^ prow[:, None], R)
+        used[np.arange(P)[piv_exists], piv[piv_exists]] = True
+        rank += piv_exists
+    return rank
+
+
+def row_masks(M):
+    k = M.shape[0]
+    return np.array([sum(int(M[i, j]) << j for j in range(k)) for i in range(k)], dtype=np.uint64)
+
+
+def all_design_vectors(orc, n):
+    k = orc.choose_k(n)
+    L = orc.design_size(k)
+    return np.stack([orc.design_vector(n, k, l) for l in range(L)]), k
+
+
+# ------------------------------------------------------------- the field ---
+
+@pytest.mark.parametrize("D", list(range(1, 12)))
+def test_field_is_a_field(orc, D):
+    """F_2[w]/p(w) is a field: every nonzero a satisfies a^(2^D - 1) = 1 (which
+    fails for a zero divisor, i.e. for reducible p), and a has an inverse."""
+    p = orc.field_poly(D)
+    assert p >> D == 1, "p must have degree D"
+    q = 1 << D
+    for a in range(1, q):
+        acc, base, e = 1, a, q - 1
+        while e:
+            if e & 1:
+                acc = orc.gf_mul(acc, base, p)
+            base = orc.gf_mul(base, base, p)
+            e >>= 1
+        assert acc == 1
+    if D <= 6:
+        for a in range(1, q):
+            assert any(orc.gf_mul(a, b, p) == 1 for b in range(1, q))
+
+
+@pytest.mark.parametrize("D", [1, 3, 5, 7, 9, 11])
+def test_multiplication_ring_axioms(orc, D):
+    """Commutative, associative, distributive over XOR (random triples)."""
+    p = orc.field_poly(D)
+    rng = np.random.default_rng(D)
+    for a, b, c in rng.integers(0, 1 << D, size=(200, 3)):
+        a, b, c = int(a), int(b), int(c)
+        assert orc.gf_mul(a, b, p) == orc.gf_mul(b, a, p)
+        assert orc.gf_mul(orc.gf_mul(a, b, p), c, p) == orc.gf_mul(a, orc.gf_mul(b, c, p), p)
+        assert orc.gf_mul(a, b ^ c, p) == orc.gf_mul(a, b, p) ^ orc.gf_mul(a, c, p)
+
+
+@pytest.mark.parametrize("D", [1, 3, 5, 7, 9, 11])
+def test_trace_properties(orc, D):
+    """The three trace facts the proof of Proposition 7 uses: F_2-linear,
+    tr(z^2) = tr(z), values in F_2; and tr is onto (half the field has tr 1)."""
+    p = orc.field_poly(D)
+    q = 1 << D
+    tr = [orc.gf_trace(z, p) for z in range(q)]
+    assert set(tr) <= {0, 1}
+    assert sum(tr) == q // 2
+    rng = np.random.default_rng(D + 100)
+    for a, b in rng.integers(0, q, size=(300, 2)):
+        a, b = int(a), int(b)
+        assert tr[a ^ b] == tr[a] ^ tr[b]
+        assert tr[orc.gf_mul(a, a, p)] == tr[a]
+
+
+# --------------------------------------------------------- the Kerdock set ---
+
+@pytest.mark.parametrize("k", [2, 4, 6, 8, 10, 12])
+def test_kerdock_set(orc, k):
+    """Proposition 7 / the definition of a Kerdock set: 2^(k-1) alternating
+    (symmetric, zero-diagonal) matrices whose pairwise sums all have full
+    rank over F_2.  Every pair is checked (2.1 million pairs at k = 12)."""
+    q = 1 << (k - 1)
+    Ms = [orc.kerdock_matrix(k, s) for s in range(q)]
+    for M in Ms:
+        assert np.array_equal(M, M.T)
+        assert not M.diagonal().any()
+    R = np.stack([row_masks(M) for M in Ms])          # (q, k)
+    # distinct first rows (the remark after the definition)
+    assert len({int(r) for r in R[:, 0]}) == q
+    for r in range(q - 1):
+        S = R[r + 1:] ^ R[r][None, :]
+        assert (gf2_rank_batch(S) == k).all(), "M_%d + M_s singular" % r
+
+
+def test_kerdock_matrix_zero_is_hadamard_basis(orc):
+    """s = 0 gives L_0 = 0, hence M_0 = 0 and Q = 0: the first basis is the
+    plain Walsh-Hadamard basis."""
+    for k in (2, 4, 6, 8):
+        assert not orc.kerdock_matrix(k, 0).any()
+
+
+def test_rank_helper_against_scalar_elimination():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        k = int(rng.integers(2, 13))
+        rows = [int(v) for v in rng.integers(0, 1 << k, size=k)]
+        assert gf2_rank(rows) == gf2_rank_batch(np.array([rows], dtype=np.uint64))[0]
+
+
+# ----------------------------------------------------- the design (bases) ---
+
+@pytest.mark.parametrize("n", [4, 16, 64])
+def test_bases_orthonormal_and_mutually_unbiased(orc, n):
+    """Proposition 6 (a), (b) for every pair of the d/2+1 bases at n = d:
+    <u, u'> = delta inside a basis and |<u, u'>|^2 = 1/d across bases."""
+    S, k = all_design_vectors(orc, n)
+    d = 1 << k
+    U = S / math.sqrt(d)
+    G = U @ U.T
+    L = U.shape[0]
+    blk = np.arange(L) // d
+    same = blk[:, None] == blk[None, :]
+    assert np.allclose(G[same].reshape(-1), np.eye(d).reshape(1, d, d).repeat(d // 2 + 1, 0).reshape(-1), atol=1e-12)
+    assert np.allclose(G[~same] ** 2, 1.0 / d, atol=1e-12)
+    # Kerdock vectors of s_l are +-1 (sqrt(d) 2^{-k/2} = 1)
+    assert set(np.unique(np.abs(S[: (d // 2) * d]))) == {1.0}
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_projective_2_design_frame_potential(orc, n):
+    """Proposition 2(c) with t = 2: the average of <u, u'>^2 is c_{d,1} = 1/d
+    and the average of <u, u'>^4 is c_{d,2} = 3/(d(d+2))."""
+    S, k = all_design_vectors(orc, n)
+    d = 1 << k
+    G = (S / math.sqrt(d)) @ (S / math.sqrt(d)).T
+    assert abs(np.mean(G ** 2) - 1.0 / d) < 1e-12
+    assert abs(np.mean(G ** 4) - 3.0 / (d * (d + 2))) < 1e-12
+
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_projective_2_design_moments(orc, n):
+    """Proposition 2(b): (1/L) sum <x,u>^2 = |x|^2/d and
+    (1/L) sum <x,u>^4 = 3|x|^4/(d(d+2)) for arbitrary x (n = d)."""
+    k = orc.choose_k(n)
+    d = 1 << k
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((3, n))
+    T = orc.table(X)                       # T[l, r] = s_l . x_r = sqrt(d) <x_r, u_l>
+    inner = T / math.sqrt(d)
+    nx = np.sum(X ** 2, axis=1)
+    assert np.allclose(np.mean(inner ** 2, axis=0), nx / d, rtol=1e-12)
+    assert np.allclose(np.mean(inner ** 4, axis=0), 3 * nx ** 2 / (d * (d + 2)), rtol=1e-11)
+
+
+def test_first_basis_is_sylvester_hadamard(orc):
+    """Block b = 0 (M_0 = 0): s_{0,w}[x] = (-1)^{popcount(x & w)}, the Sylvester
+    Hadamard matrix of scipy."""
+    for n in (16, 64):
+        k = orc.choose_k(n)
+        H = scipy.linalg.hadamard(1 << k)
+        for w in range(1 << k):
+            assert np.array_equal(orc.design_vector(n, k, w), H[:, w][:n].astype(float))
+
+
+@pytest.mark.parametrize("n", [12, 50])
+def test_projection_keeps_first_coordinates(orc, n):
+    """Pi keeps coordinates 0..n-1 of the length-d vector (n < d)."""
+    k = orc.choose_k(n)
+    d = 1 << k
+    for l in [0, 5, d + 3, (d // 2) * d + 2, (d // 2) * d + n - 1, (d // 2) * d + n]:
+        full = orc.design_vector(d, k, l)
+        assert np.array_equal(orc.design_vector(n, k, l), full[:n])
+
+
+def test_choose_k_is_power_of_four(orc):
+    expect = {1: 2, 2: 2, 4: 2, 5: 4, 16: 4, 17: 6, 64: 6, 100: 8, 256: 8, 1000: 10,
+              1024: 10, 2048: 12, 4096: 12}
+    for n, k in expect.items():
+        assert orc.choose_k(n) == k
+    # the only design size the paper prints: L = 8,392,704 at n = 4096
+    assert orc.design_size(12) == 8392704
+
+
+# ------------------------------------------------------ the sketch tables ---
+
+@pytest.mark.parametrize("n", [16, 50, 64])
+def test_table_reproduces_Ax_per_basis_and_in_full(orc, n):
+    """Equation (1) with the 2-design: for every basis b, (1/d) sum_w
+    T[b,w] (s_{b,w}^T x) = Ax, and (1/L) sum_l T[l] (s_l^T x) = Ax.  A is
+    non-symmetric, so a transposed operand fails."""
+    rng = np.random.default_rng(n + 7)
+    m = n + 3
+    A = rng.standard_normal((m, n))
+    x = rng.standard_normal(n)
+    k = orc.choose_k(n)
+    d = 1 << k
+    T = orc.table(A)
+    S = np.stack([orc.design_vector(n, k, l) for l in range(T.shape[0])])
+    c = S @ x
+    Ax = A @ x
+    for b in range(d // 2 + 1):
+        est = (T[b * d:(b + 1) * d] * c[b * d:(b + 1) * d, None]).sum(0) / d
+        assert np.allclose(est, Ax, atol=1e-10)
+    assert np.allclose((T * c[:, None]).sum(0) / T.shape[0], Ax, atol=1e-10)
+
+
+def test_table_first_basis_is_A_times_hadamard(orc):
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((20, 64))
+    T = orc.table(A)
+    H = scipy.linalg.hadamard(64).astype(float)
+    assert np.allclose(T[:64], (A @ H).T, atol=1e-11)
+    # identity block: sqrt(d) A e_w
+    assert np.allclose(T[32 * 64:], 8.0 * A.T, atol=1e-12)
+
+
+# ------------------------------------------------ the estimator (Lemma 4) ---
+
+@pytest.mark.parametrize("n", [12, 16, 50, 64])
+def test_estimator_mean_and_exact_variance(orc, n):
+    """Lemma 4 by enumeration of all L equally likely draws: E[y_i] = (Ax)_i
+    and Var(y_i) = 2 a1^2 (d-1)/(d+2) + a2^2 d/(d+2), with a1 = a_i.x and
+    a2^2 = |a_i|^2 - a1^2 (x unit); this holds also with projection n < d."""
+    rng = np.random.default_rng(11 * n)
+    m = 9
+    A = rng.standard_normal((m, n))
+    x = rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    k = orc.choose_k(n)
+    d = 1 << k
+    T = orc.table(A)
+    S = np.stack([orc.design_vector(n, k, l) for l in range(T.shape[0])])
+    Y = T * (S @ x)[:, None]                       # y for every draw, (L, m)
+    a1 = A @ x
+    a2sq = np.sum(A ** 2, axis=1) - a1 ** 2
+    assert np.allclose(Y.mean(0), a1, atol=1e-10)
+    var = 2 * a1 ** 2 * (d - 1) / (d + 2) + a2sq * d / (d + 2)
+    assert np.allclose(Y.var(0), var, rtol=1e-9, atol=1e-10)
+    assert (Y.var(0) <= 2 * np.sum(A ** 2, axis=1) + 1e-9).all()
+
+
+# ------------------------------------------------------------ sampling ---
+
+def _numpy_philox_block(ctr_words, key_words):
+    """Philox4x64-10 block at counter c via numpy, which increments its
+    counter before every block: start it at c - 1."""
+    c = sum(int(w) << (64 * i) for i, w in enumerate(ctr_words))
+    c = (c - 1) % (1 << 256)
+    key = int(key_words[0]) + (int(key_words[1]) << 64)
+    g = np.random.Philox(key=key, counter=c)
+    return g.random_raw(4)
+
+
+def test_philox_against_numpy(orc):
+    rng = np.random.default_rng(17)
+    cases = [([0, 0, 0, 0], [0, 0]), ([1, 0, 0, 0], [0, 0]), ([0, 5, 0, 0], [123, 0]),
+             ([2 ** 64 - 1, 3, 0, 0], [2 ** 63, 7])]
+    for _ in range(20):
+        cases.append(([int(v) for v in rng.integers(0, 2 ** 63, size=4)],
+                      [int(v) for v in rng.integers(0, 2 ** 63, size=2)]))
+    for ctr, key in cases:
+        assert np.array_equal(orc.philox4x64_10(ctr, key), _numpy_philox_block(ctr, key))
+
+
+@pytest.mark.parametrize("k", [4, 10, 12])
+def test_draw_samples_mapping(orc, k):
+    """l_j = floor(r L / 2^64) with r the (j mod 4)-th word of the block at
+    counter (floor(j/4), t, 0, 0), key (seed, 0)."""
+    L = orc.design_size(k)
+    seed, t, N = 99, 1234567, 37
+    ls = orc.draw_samples(seed, t, N, L)
+    for j in range(N):
+        r = int(_numpy_philox_block([j // 4, t, 0, 0], [seed, 0])[j % 4])
+        assert ls[j] == (r * L) >> 64
+    assert ls.min() >= 0 and ls.max() < L
+
+
+def test_draw_samples_uniform(orc):
+    """chi-square test of the (basis, vector) coordinates at k = 4."""
+    k, d = 4, 16
+    L = orc.design_size(k)
+    ls = orc.draw_samples(5, 0, 200000, L)
+    counts = np.bincount(ls, minlength=L)
+    exp = len(ls) / L
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    # dof = L - 1 = 143; 99.99% quantile ~ 212
+    assert chi2 < 212
+    assert np.bincount(ls // d, minlength=d // 2 + 1).min() > 0
+
+
+# ---------------------------------------------------------- quantisers ---
+
+def test_bf16_quantiser_matches_torch(orc):
+    rng = np.random.default_rng(4)
+    v = (rng.standard_normal(4000) * np.exp(rng.uniform(-20, 20, 4000))).astype(np.float32)
+    v = np.concatenate([v, np.float32([0.0, 1.0, -1.0, 1.00390625, 1.01171875, 3.4e38, 1e-39])])
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    got = orc.quant_bf16(v.astype(np.float64))
+    assert np.array_equal(got, want)
+
+
+def test_e4m3_quantiser_matches_torch(orc):
+    rng = np.random.default_rng(6)
+    v = (rng.uniform(-448, 448, 4000) * np.exp(rng.uniform(-12, 0, 4000))).astype(np.float32)
+    # every code point and every midpoint between neighbouring codes (ties)
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    codes = np.unique(codes[np.isfinite(codes)])
+    mids = (codes[1:] + codes[:-1]) / 2
+    v = np.concatenate([v, codes.astype(np.float32), mids.astype(np.float32)])
+    want = torch.from_numpy(v).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = orc.quant_e4m3(v.astype(np.float64))
+    assert np.array_equal(got, want)
+    assert orc.quant_e4m3(1000.0) == 448.0 and orc.quant_e4m3(-460.0) == -448.0
+
+
+# ------------------------------------------------ the streaming pipeline ---
+
+def _pipeline_by_numpy(orc, A, x, J, K, s_max, eps, samples, table_fn):
+    """Recompute every streaming step from the oracle's drawn samples with
+    numpy routines: columns, coefficients, batch means, numpy's median (mean
+    of the two middle values for even K), a lexsort top-s_max and A_S x."""
+    m, n = A.shape
+    k = orc.choose_k(n)
+    cols = np.stack([table_fn(l) for l in samples])
+    coef = np.stack([orc.design_vector(n, k, l) for l in samples]) @ x
+    Y = cols * coef[:, None]
+    ybar = Y.reshape(K, J, m).mean(1)
+    mu = np.median(ybar, axis=0)
+    order = np.lexsort((np.arange(m), -np.abs(mu)))
+    S = np.sort(order[:s_max])
+    v = A[S] @ x
+    keep = np.abs(v) >= eps
+    return coef, ybar, mu, S, S[keep], v[keep]
+
+
+@pytest.mark.parametrize("J,K", [(7, 1), (5, 2), (4, 3), (3, 4), (2, 5)])
+def test_sparse_apply_steps_against_numpy(orc, J, K):
+    w = workloads.tiny(batch=3)
+    A = w.A.astype(np.float64)
+    X = w.X.astype(np.float64)
+    s_max = 10
+    r = orc.sparse_apply(A, X, J, K, 0.02, s_max, seed=3001, t0=40, debug=True)
+    L = orc.design_size(orc.choose_k(A.shape[1]))
+    for t in range(X.shape[0]):
+        samples = orc.draw_samples(3001, 40 + t, J * K, L)
+        assert np.array_equal(r["samples"][t], samples)
+        coef, ybar, mu, S, idx, val = _pipeline_by_numpy(
+            orc, A, X[t], J, K, s_max, 0.02, samples, lambda l: orc.table_column(A, l))
+        assert np.allclose(r["coef"][t], coef, rtol=1e-12, atol=1e-12)
+        assert np.allclose(r["ybar"][t], ybar, rtol=1e-12, atol=1e-12)
+        assert np.allclose(r["mu"][t], mu, rtol=1e-12, atol=1e-12)
+        assert np.array_equal(r["surv"][t], S)
+        c = r["out_cnt"][t]
+        assert np.array_equal(r["out_idx"][t][:c], idx)
+        assert np.allclose(r["out_val"][t][:c], val, rtol=1e-12)
+        assert (r["out_idx"][t][c:] == -1).all()
+
+
+def test_two_batches_median_is_the_mean(orc):
+    """With K = 2 the median of means is the plain mean of all N draws."""
+    w = workloads.tiny(batch=2)
+    A = w.A.astype(np.float64)
+    r = orc.sparse_apply(A, w.X, 9, 2, 0.1, 8, seed=7, debug=True)
+    L = orc.design_size(6)
+    for t in range(2):
+        s = r["samples"][t]
+        Y = np.stack([orc.table_column(A, l) for l in s]) * r["coef"][t][:, None]
+        assert np.allclose(r["mu"][t], Y.mean(0), atol=1e-12)
+
+
+def test_full_enumeration_recovers_h_eps(orc):
+    """Special case: the exact expectation.  With the whole design enumerated
+    once (the estimator replaced by its mean, which equals Ax by Lemma 4),
+    the top-s rows and the threshold give h_eps(Ax) exactly."""
+    w = workloads.tiny(batch=4)
+    A = w.A.astype(np.float64)
+    T = orc.table(A)
+    S = np.stack([orc.design_vector(64, 6, l) for l in range(T.shape[0])])
+    for x in w.X.astype(np.float64):
+        mu = (T * (S @ x)[:, None]).mean(0)
+        Ax = A @ x
+        assert np.allclose(mu, Ax, atol=1e-12)
+        top = np.sort(np.lexsort((np.arange(64), -np.abs(mu)))[:8])
+        keep = top[np.abs(Ax[top]) >= w.eps]
+        assert set(keep) == set(np.nonzero(np.abs(Ax) >= w.eps)[0])
+
+
+def test_quantised_tables_in_pipeline(orc):
+    """Table modes: each sampled entry is replaced by its bf16 rounding, or by
+    scale_i * e4m3(T / scale_i) with scale_i = fl32(max(|a_i|_1,
+    sqrt(d)|a_i|_inf)/448)."""
+    w = workloads.tiny(batch=2)
+    A = w.A.astype(np.float64)
+    d = 64
+    scale = np.maximum(np.abs(A).sum(1), np.sqrt(d) * np.abs(A).max(1)) / 448.0
+    scale = scale.astype(np.float32).astype(np.float64)
+    for mode, fn in [("bf16", lambda l: orc.quant_bf16(orc.table_column(A, l))),
+                     ("fp8", lambda l: scale * orc.quant_e4m3(orc.table_column(A, l) / scale))]:
+        r = orc.sparse_apply(A, w.X, 6, 3, 0.1, 8, seed=11, table_mode=mode, debug=True)
+        for t in range(2):
+            s = r["samples"][t]
+            _, ybar, mu, S, idx, val = _pipeline_by_numpy(orc, A, w.X[t].astype(np.float64), 6, 3, 8, 0.1, s, fn)
+            assert np.allclose(r["mu"][t], mu, atol=1e-12)
+            assert np.array_equal(r["surv"][t], S)
+    # the scale bounds every entry of every column, so nothing saturates
+    T = orc.table(A)
+    assert (np.abs(T) <= 448.0 * scale[None, :] * (1 + 1e-6)).all()
+
+
+def test_theorem5_failure_rate(orc):
+    """Theorem 5: with J >= 4 e^2 |A|_{2->inf}^2 / gamma^2 and
+    K >= 2 log(m/eta), |mu - Ax|_inf < gamma with probability >= 1 - eta."""
+    n = 16
+    A = workloads.haar_orthogonal(n, np.random.default_rng(8))     # |A|_{2->inf} = 1
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((60, n))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    gamma, eta = 0.6, 0.5
+    J = math.ceil(4 * math.e ** 2 / gamma ** 2)
+    K = math.ceil(2 * math.log(n / eta))
+    r = orc.sparse_apply(A, X, J, K, 0.1, 4, seed=21, debug=True)
+    err = np.abs(r["mu"] - X @ A.T).max(1)
+    assert np.mean(err >= gamma) <= eta
+    # and the estimate is far from exact with a single small batch
+    r1 = orc.sparse_apply(A, X, 1, 1, 0.1, 4, seed=21, debug=True)
+    assert np.mean(np.abs(r1["mu"] - X @ A.T).max(1) >= gamma) > eta
+
+
+def test_deterministic_and_stream_position(orc):
+    w = workloads.tiny(batch=3)
+    a = orc.sparse_apply(w.A, w.X, 5, 2, 0.1, 8, seed=1, t0=10, debug=True)
+    b = orc.sparse_apply(w.A, w.X, 5, 2, 0.1, 8, seed=1, t0=10, debug=True)
+    for key in a:
+        assert np.array_equal(a[key], b[key])
+    c = orc.sparse_apply(w.A, w.X[1:], 5, 2, 0.1, 8, seed=1, t0=11, debug=True)
+    assert np.array_equal(c["samples"], a["samples"][1:])
+
+
+def test_invalid_arguments(orc):
+    w = workloads.tiny()
+    for kw in [dict(J=0, K=1, eps=0.1, s_max=4), dict(J=1, K=0, eps=0.1, s_max=4),
+               dict(J=1, K=1, eps=0.0, s_max=4), dict(J=1, K=1, eps=0.1, s_max=0),
+               dict(J=1, K=1, eps=0.1, s_max=65)]:
+        with pytest.raises(ValueError):
+            orc.sparse_apply(w.A, w.X, seed=0, **kw)
