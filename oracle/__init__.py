@@ -53,6 +53,8 @@ def _load():
         "ko_draw_samples": (None, [c_u64, c_i64, c_i64, c_i64, c_p]),
         "ko_quant_bf16": (c_d, [c_d]),
         "ko_quant_e4m3": (c_d, [c_d]),
+        "ko_sign_words": (None, [c_i, c_u64, c_p]),
+        "ko_mu_rows": (None, [c_p, c_i, c_i, c_p, c_p, c_i, c_i, c_p, c_i, c_i, c_p]),
         "ko_sparse_apply": (c_i, [c_p, c_i, c_i, c_p, c_i, c_i64, c_u64, c_i, c_i, c_d, c_i,
                                   c_d, c_i, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
     }
@@ -151,6 +153,27 @@ def quant_bf16(x):
 def quant_e4m3(x):
     f = _load().ko_quant_e4m3
     return np.vectorize(lambda v: f(float(v)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+
+
+def sign_words(k, s):
+    """(-1)^{Q_{M_s}(x)} for x < d as bit x mod 32 of word x // 32."""
+    out = np.zeros(max(1, (1 << k) // 32), dtype=np.uint32)
+    _load().ko_sign_words(int(k), int(s), _ptr(out))
+    return out
+
+
+def mu_rows(A, x, samples, J, K, rows, table_mode="exact"):
+    """Median-of-means estimate on the given rows from given draws."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    ls = np.ascontiguousarray(samples, dtype=np.int64)
+    assert ls.size == J * K and K <= 64
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros(rows.size, dtype=np.float64)
+    _load().ko_mu_rows(_ptr(A), m, n, _ptr(x), _ptr(ls), int(J), int(K), _ptr(rows), rows.size,
+                       TABLE_MODES[table_mode], _ptr(out))
+    return out
 
 
 TABLE_MODES = {"f32": 0, "exact": 0, "bf16": 1, "fp8": 2, "fp8e4m3": 2}

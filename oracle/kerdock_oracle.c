@@ -200,6 +200,20 @@ void ko_design_vector(int n, int k, int64_t l, double *s_out)
     }
 }
 
+/* the signs (-1)^{Q_M(x)} of Kerdock basis s, x < d, packed as bit x mod 32
+ * of word x / 32 (the layout the GPU library reports) */
+void ko_sign_words(int k, uint64_t s, uint32_t *words)
+{
+    int64_t d = (int64_t)1 << k;
+    int64_t nw = d >= 32 ? d / 32 : 1;
+    uint8_t M[64 * 64];
+    ko_kerdock_matrix(k, s, M);
+    for (int64_t q = 0; q < nw; q++) words[q] = 0;
+    for (int64_t x = 0; x < d; x++)
+        if (ko_quadratic_form(k, M, (uint64_t)x))
+            words[x / 32] |= (uint32_t)1 << (x % 32);
+}
+
 /* sketch column A s_l (A row-major m x n), a plain matrix-vector product */
 void ko_table_column(const double *A, int m, int n, int k, int64_t l, double *col)
 {
@@ -330,6 +344,54 @@ static double median_of(double *v, int K)
     }
     if (K % 2) return v[K / 2];
     return 0.5 * (v[K / 2 - 1] + v[K / 2]);
+}
+
+/*
+ * The median-of-means estimate restricted to chosen rows, for one vector x
+ * and given draws l_j (j < J K): mu_r = median_k (1/J) sum_{j in batch k}
+ * T[l_j]_r (s_lj^T x) for r in rows[].  T[l]_r = a_r . s_l (plain dot
+ * product), optionally quantised as in ko_sparse_apply.
+ */
+void ko_mu_rows(const double *A, int m, int n, const double *x, const int64_t *ls, int J, int K,
+                const int32_t *rows, int nrows, int table_mode, double *mu_out)
+{
+    int k = ko_choose_k(n);
+    int64_t d = (int64_t)1 << k;
+    int64_t N = (int64_t)J * K;
+    double *c = (double *)malloc(sizeof(double) * (size_t)N);
+    double *s = (double *)malloc(sizeof(double) * (size_t)n);
+    double *S = (double *)malloc(sizeof(double) * (size_t)N * n);
+    for (int64_t j = 0; j < N; j++) {
+        ko_design_vector(n, k, ls[j], S + (size_t)j * n);
+        double acc = 0.0;
+        for (int q = 0; q < n; q++) acc += S[(size_t)j * n + q] * x[q];
+        c[j] = acc;
+    }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < nrows; r++) {
+        int i = rows[r];
+        const double *a = A + (size_t)i * n;
+        double l1 = 0.0, linf = 0.0;
+        for (int q = 0; q < n; q++) { double v = fabs(a[q]); l1 += v; if (v > linf) linf = v; }
+        double bound = l1 > sqrt((double)d) * linf ? l1 : sqrt((double)d) * linf;
+        double scale = (double)(float)(bound / 448.0);
+        if (scale == 0.0) scale = 1.0;
+        double kv[64];
+        for (int kb = 0; kb < K; kb++) {
+            double acc = 0.0;
+            for (int64_t j = (int64_t)kb * J; j < (int64_t)(kb + 1) * J; j++) {
+                const double *sj = S + (size_t)j * n;
+                double Ti = 0.0;
+                for (int q = 0; q < n; q++) Ti += a[q] * sj[q];
+                if (table_mode == 1) Ti = ko_quant_bf16(Ti);
+                else if (table_mode == 2) Ti = scale * ko_quant_e4m3(Ti / scale);
+                acc += Ti * c[j];
+            }
+            kv[kb] = acc / (double)J;
+        }
+        mu_out[r] = median_of(kv, K);
+    }
+    free(c); free(s); free(S);
 }
 
 /*
