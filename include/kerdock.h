@@ -1,0 +1,177 @@
+/*
+ * kerdock.h -- C ABI of the MI355X (gfx950) Kerdock fast sparsifying
+ * transform: Fuchs, Gross, Krahmer, Kueng, Mixon, "Sketching with Kerdock's
+ * crayons: fast sparsifying transforms for arbitrary linear maps",
+ * arXiv 2105.05879.
+ *
+ * The library solves Problem 1 of the paper with Algorithm 1: it preprocesses
+ * an arbitrary A in R^{m x n} once into the sketch {A s_l : l in [L]} of a
+ * Kerdock-set projective 2-design (Lemma 8), and then, for a stream of unit
+ * vectors x, returns the epsilon-hard threshold h_eps(Ax) restricted to the
+ * rows that a median-of-means estimate (Theorem 5) ranks highest.
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers are HIP device allocations on the current device
+ *     (torch tensors' data_ptr() qualify).  Host pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued asynchronously on it; outputs are valid once the
+ *     stream has been synchronised.  Prepare synchronises before returning.
+ *   - Matrices are row-major FP32.  X holds one vector per row.
+ *   - Return value: KERDOCK_OK (0) or a negative kerdock_status; the last
+ *     error message of the calling thread is kerdock_last_error().
+ *   - A handle owns all the device memory it allocates (tables, a copy of A,
+ *     sign bitmaps, a growable workspace); kerdock_destroy frees it.  The
+ *     caller keeps ownership of every pointer it passes.  Calls on one
+ *     handle must not overlap (they share its workspace).
+ */
+#ifndef KERDOCK_H
+#define KERDOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kerdock_handle_s *kerdock_handle;
+
+/* Element type of the stored sketch tables.  FP32 is the plain method;
+ * BF16 (round to nearest even) and FP8 E4M3 (OCP format, max 448, saturating
+ * round to nearest even, divided by a per-row FP32 scale) are the precision
+ * forms.  Accumulation is FP32 in every case. */
+typedef enum {
+    KERDOCK_F32 = 0,
+    KERDOCK_BF16 = 1,
+    KERDOCK_FP8E4M3 = 2
+} kerdock_dtype;
+
+typedef enum {
+    KERDOCK_OK = 0,
+    KERDOCK_ERR_INVALID_ARG = -1,   /* bad size, pointer, eps, s_max, J, K ... */
+    KERDOCK_ERR_UNSUPPORTED_N = -2, /* n outside [1, 4096] (d = 16384 beyond) */
+    KERDOCK_ERR_OOM = -3,           /* a device allocation failed            */
+    KERDOCK_ERR_HIP = -4,           /* a HIP runtime call or launch failed   */
+    KERDOCK_ERR_NOT_PREPARED = -5   /* NULL or destroyed handle              */
+} kerdock_status;
+
+/* Geometry of a prepared handle (Algorithm 1, preprocessing step). */
+typedef struct {
+    int32_t m, n;          /* A is m x n                                      */
+    int32_t k;             /* smallest even k with d = 2^k >= n (Lemma 8)     */
+    int32_t d;             /* 2^k                                             */
+    int64_t L;             /* design size d (d/2 + 1)                         */
+    int32_t pitch;         /* elements between consecutive table columns     */
+    uint32_t field_poly;   /* irreducible polynomial of F_{2^{k-1}} (bits)   */
+    kerdock_dtype dtype;
+    size_t table_bytes;    /* bytes of the sketch table in device memory      */
+} kerdock_info;
+
+/* Streaming parameters (Algorithm 1 streaming step, Theorem 5).  A zeroed
+ * struct is invalid (J = K = 0): set J and K. */
+typedef struct {
+    int32_t J;             /* samples per batch                               */
+    int32_t K;             /* number of batches; N = J K draws per x          */
+    uint64_t seed;         /* key of the Philox4x64-10 draws                  */
+    int64_t t0;            /* stream position of X row 0: draw j of row t is a
+                              pure function of (seed, t0 + t, j)              */
+    float tau;             /* optional floor on |mu| inside S (0 = none)      */
+    /* optional device outputs for parity checks (NULL = not written):       */
+    uint32_t *dbg_samples; /* [batch][N] drawn design indices l_j             */
+    float *dbg_coef;       /* [batch][N] s_{l_j}^T x                          */
+    float *dbg_mu;         /* [batch][m] median-of-means estimate             */
+    int32_t *dbg_survivors;/* [batch][s_max] S ascending, -1 padded           */
+    float *dbg_values;     /* [batch][s_max] a_i.x for every i in S, 0 padded */
+} kerdock_apply_params;
+
+/*
+ * kerdock_prepare -- preprocessing step of Algorithm 1 via Lemma 8.
+ *   A       device, m x n row-major FP32 (read; copied into the handle).
+ *   m, n    1 <= m <= 16384, 1 <= n <= 4096.
+ *   dtype   element type of the stored table.
+ *   stream  HIP stream (void*); prepare synchronises it before returning.
+ *   out     host; receives the new handle.
+ * Builds, for k even with d = 2^k >= n and L = d(d/2+1), the table column
+ * T[l] = A s_l for every l = b d + w: Kerdock blocks b < d/2 use the vectors
+ * (-1)^{Q_b(x) + w.x} of equation (3) with the Kerdock matrices of
+ * Proposition 7 (computed as a fast Walsh-Hadamard transform of A's signed
+ * rows); block b = d/2 is the identity basis, T[l] = sqrt(d) A e_w (zero for
+ * w >= n).  Errors: INVALID_ARG (NULL pointer, m < 1, m > 16384), UNSUPPORTED_N,
+ * OOM (table larger than free device memory), HIP.
+ */
+int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *stream,
+                    kerdock_handle *out);
+
+/*
+ * kerdock_sparse_apply -- streaming step of Algorithm 1 for `batch` vectors.
+ *   X        device, batch x n row-major FP32, rows are unit vectors (the
+ *            library does not normalise them: Problem 1 assumes unit x).
+ *   batch    >= 0 (0 is a no-op).
+ *   eps      > 0, the hard threshold of Problem 1 (|v| >= eps is kept).
+ *   s_max    1 <= s_max <= m: size of S, the rows of largest |mu| (the
+ *            numerical section uses 10 s).
+ *   p        host; J >= 1, K >= 1 and the optional fields above.
+ *   out_idx  device [batch][s_max] int32: kept row indices, ascending,
+ *            padded with -1.
+ *   out_val  device [batch][s_max] FP32: (Ax)_i for the kept rows, computed
+ *            exactly from FP32 A and x (compensated dot product), 0 padded.
+ *   out_cnt  device [batch] int32: number of kept rows.
+ * For every row x: draws l_j (j < N) uniformly from [L]; forms
+ * y_j = T[l_j] (s_{l_j}^T x); averages each batch of J draws; takes the
+ * entrywise median of the K means (the mean of the two middle values for
+ * even K); selects S = the s_max rows of largest |mu| (ties: smaller index),
+ * optionally only those with |mu| >= tau; computes a_i.x for i in S and
+ * keeps |a_i.x| >= eps.  May grow the handle's workspace (hipMalloc) unless
+ * kerdock_reserve was called with sizes at least as large.
+ * Errors: NOT_PREPARED, INVALID_ARG (NULL pointers with batch > 0, eps <= 0
+ * or NaN, s_max out of range, J < 1, K < 1, K > 32, J K > 2^31), OOM, HIP.
+ */
+int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                         const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                         int32_t *out_cnt, void *stream);
+
+/*
+ * kerdock_reserve -- allocate the workspace that kerdock_sparse_apply needs
+ * for up to `batch` vectors with N = J K draws and the given s_max, so that
+ * later calls within these sizes allocate nothing (needed before capturing
+ * the calls in a HIP graph).  Errors: NOT_PREPARED, INVALID_ARG, OOM.
+ */
+int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max);
+
+/* kerdock_query -- geometry of a handle; `info` is host memory. */
+int kerdock_query(kerdock_handle h, kerdock_info *info);
+
+/*
+ * kerdock_read_columns -- dequantised table columns, for parity checks.
+ *   ells  device [count] uint32 design indices (< L).
+ *   out   device [count][m] FP32: T[l] as stored (times the row scale for
+ *         FP8 tables).
+ */
+int kerdock_read_columns(kerdock_handle h, const uint32_t *ells, int count, float *out,
+                         void *stream);
+
+/*
+ * kerdock_debug_signs -- the sign pattern (-1)^{Q_b(x)} of Kerdock basis
+ * b < d/2 (equation (3) with w = 0), as d/32 host words: bit x mod 32 of word
+ * x / 32 is Q_b(x).  Synchronous.
+ */
+int kerdock_debug_signs(kerdock_handle h, int b, uint32_t *out_bits);
+
+/*
+ * kerdock_row_scales -- per-row FP32 scales of an FP8 table (1 for the other
+ * dtypes): max(|a_i|_1, sqrt(d) |a_i|_inf) / 448, a bound on every |T[l]_i|.
+ *   out  device [m].
+ */
+int kerdock_row_scales(kerdock_handle h, float *out, void *stream);
+
+/* kerdock_destroy -- free every device allocation of the handle. */
+int kerdock_destroy(kerdock_handle h);
+
+/* kerdock_last_error -- message of the last failing call on this thread. */
+const char *kerdock_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KERDOCK_H */

@@ -1,0 +1,304 @@
+// C ABI of the Kerdock fast sparsifying transform (include/kerdock.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace kd {
+
+uint32_t field_polynomial(int D);
+std::vector<uint16_t> kerdock_masks(int k, uint32_t *poly_out);
+
+int launch_signs(const uint16_t *masks, int k, uint32_t *signs, hipStream_t s);
+int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dtype dt,
+                      float *scales, hipStream_t s);
+int launch_table_build(kerdock_dtype dt, int k, const float *A, int m, int n, int pitch,
+                       const uint32_t *signs, const float *scales, void *table, hipStream_t s);
+int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, int64_t L,
+                        const float *scales, const uint32_t *ells, int count, float *out,
+                        hipStream_t s);
+int launch_sample_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs,
+                       uint64_t seed, int64_t t0, int N, uint32_t *samples, float *coef,
+                       hipStream_t s);
+int launch_gather(kerdock_dtype dt, const void *table, int pitch, const uint32_t *samples,
+                  const float *coef, int batch, int N, int J, int K, int chunk, int unroll,
+                  float *partial, hipStream_t s);
+int launch_select(const float *partial, int batch, int m, int pitch, int K, int cpb, int J,
+                  const float *scales, int s_max, float tau, float *mu_out, int32_t *surv,
+                  int32_t *nsurv, hipStream_t s);
+int launch_survivors(const float *A, int n, const float *X, int batch, const int32_t *surv,
+                     const int32_t *nsurv, int s_max, float eps, int32_t *out_idx, float *out_val,
+                     int32_t *out_cnt, float *dbg_values, hipStream_t s);
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? KERDOCK_ERR_OOM : KERDOCK_ERR_HIP;
+}
+
+// Streaming-step tuning: draws per gather chunk and loads in flight per
+// thread.  Overridable with KERDOCK_CHUNK / KERDOCK_UNROLL.
+static int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+static int gather_chunk(int J) {
+    int c = env_int("KERDOCK_CHUNK", 512);
+    if (c < 16) c = 16;
+    return c < J ? c : J;
+}
+
+static int gather_unroll() {
+    int u = env_int("KERDOCK_UNROLL", 8);
+    return (u == 4 || u == 16) ? u : 8;
+}
+
+// workspace layout of the streaming step
+struct Workspace {
+    size_t samples, coef, partial, surv, nsurv, total;
+};
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max) {
+    const size_t N = (size_t)J * K;
+    const int chunk = gather_chunk(J);
+    const size_t cpb = (J + chunk - 1) / chunk;
+    Workspace w;
+    size_t off = 0;
+    w.samples = off; off += align256((size_t)batch * N * 4);
+    w.coef = off;    off += align256((size_t)batch * N * 4);
+    w.partial = off; off += align256((size_t)batch * K * cpb * h->pitch * 4);
+    w.surv = off;    off += align256((size_t)batch * s_max * 4);
+    w.nsurv = off;   off += align256((size_t)batch * 4);
+    w.total = off;
+    return w;
+}
+
+static int ensure_workspace(kerdock_handle_s *h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return KERDOCK_OK;
+    if (h->ws) {
+        KD_HIP(hipDeviceSynchronize());
+        KD_HIP(hipFree(h->ws));
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->ws, bytes);
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        return fail(KERDOCK_ERR_OOM, "workspace allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    h->ws_bytes = bytes;
+    return KERDOCK_OK;
+}
+
+static void free_handle(kerdock_handle_s *h) {
+    if (!h) return;
+    hipFree(h->table);
+    hipFree(h->scales);
+    hipFree(h->A);
+    hipFree(h->signs);
+    hipFree(h->masks);
+    hipFree(h->ws);
+    delete h;
+}
+
+}  // namespace kd
+
+using namespace kd;
+
+extern "C" {
+
+const char *kerdock_last_error(void) { return g_error.c_str(); }
+
+int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *stream,
+                    kerdock_handle *out) {
+    if (!out) return fail(KERDOCK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!A) return fail(KERDOCK_ERR_INVALID_ARG, "A is NULL");
+    if (m < 1 || m > 16384) return fail(KERDOCK_ERR_INVALID_ARG, "m must lie in [1, 16384]");
+    if (n < 1 || n > 4096)
+        return fail(KERDOCK_ERR_UNSUPPORTED_N, "n must lie in [1, 4096] (n > 4096 needs d = 16384)");
+    if (dtype != KERDOCK_F32 && dtype != KERDOCK_BF16 && dtype != KERDOCK_FP8E4M3)
+        return fail(KERDOCK_ERR_INVALID_ARG, "unknown dtype");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    kerdock_handle_s *h = new kerdock_handle_s();
+    h->m = m;
+    h->n = n;
+    h->k = 2;
+    while ((1 << h->k) < n) h->k += 2;
+    h->d = 1 << h->k;
+    h->L = (int64_t)h->d * (h->d / 2 + 1);
+    h->pitch = column_pitch(m);
+    h->dtype = dtype;
+    KD_HIP(hipGetDevice(&h->device));
+
+    std::vector<uint16_t> masks = kerdock_masks(h->k, &h->poly);
+    const size_t nb = (size_t)h->d / 2;
+    const size_t wpb = h->d >= 32 ? (size_t)h->d / 32 : 1;
+    h->table_bytes = (size_t)h->L * h->pitch * dtype_bytes(dtype);
+
+    size_t free_b = 0, total_b = 0;
+    KD_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t side = (size_t)m * n * 4 + nb * wpb * 4 + masks.size() * 2 + (size_t)h->pitch * 4;
+    if (h->table_bytes + side + ((size_t)1 << 28) > free_b) {
+        delete h;
+        return fail(KERDOCK_ERR_OOM, "table of " + std::to_string(h->table_bytes) +
+                                         " bytes does not fit in free device memory");
+    }
+#define KD_ALLOC(ptr, bytes)                                                      \
+    do {                                                                          \
+        hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                      \
+        if (e_ != hipSuccess) {                                                   \
+            free_handle(h);                                                       \
+            return fail(KERDOCK_ERR_OOM, std::string("allocation failed: ") + #ptr); \
+        }                                                                         \
+    } while (0)
+    KD_ALLOC(h->table, h->table_bytes);
+    KD_ALLOC(h->scales, (size_t)h->pitch * 4);
+    KD_ALLOC(h->A, (size_t)m * n * 4);
+    KD_ALLOC(h->signs, nb * wpb * 4);
+    KD_ALLOC(h->masks, masks.size() * 2);
+#undef KD_ALLOC
+
+    int rc = KERDOCK_OK;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(h->A, A, (size_t)m * n * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(h->masks, masks.data(), masks.size() * 2, hipMemcpyHostToDevice, s)) !=
+            hipSuccess) {
+        rc = hip_fail(e, "prepare copies");
+    }
+    if (rc == KERDOCK_OK) rc = launch_signs(h->masks, h->k, h->signs, s);
+    if (rc == KERDOCK_OK) rc = launch_row_scales(h->A, m, n, h->pitch, h->d, dtype, h->scales, s);
+    if (rc == KERDOCK_OK)
+        rc = launch_table_build(dtype, h->k, h->A, m, n, h->pitch, h->signs, h->scales, h->table, s);
+    if (rc == KERDOCK_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "prepare");
+    if (rc != KERDOCK_OK) {
+        free_handle(h);
+        return rc;
+    }
+    *out = h;
+    return KERDOCK_OK;
+}
+
+int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (batch < 0 || J < 1 || K < 1 || K > 32 || s_max < 1 || s_max > h->m)
+        return fail(KERDOCK_ERR_INVALID_ARG, "reserve: invalid sizes");
+    KD_HIP(hipSetDevice(h->device));
+    return ensure_workspace(h, workspace_layout(h, batch, J, K, s_max).total);
+}
+
+int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                         const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                         int32_t *out_cnt, void *stream) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!p) return fail(KERDOCK_ERR_INVALID_ARG, "params is NULL");
+    if (batch < 0) return fail(KERDOCK_ERR_INVALID_ARG, "batch < 0");
+    if (!(eps > 0.f) || !isfinite(eps)) return fail(KERDOCK_ERR_INVALID_ARG, "eps must be > 0");
+    if (s_max < 1 || s_max > h->m) return fail(KERDOCK_ERR_INVALID_ARG, "s_max must lie in [1, m]");
+    if (p->J < 1 || p->K < 1 || p->K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "need J >= 1, 1 <= K <= 32");
+    if ((int64_t)p->J * p->K > ((int64_t)1 << 31) - 64)
+        return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
+    if (batch == 0) return KERDOCK_OK;
+    if (!X || !out_idx || !out_val || !out_cnt)
+        return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int J = p->J, K = p->K, N = J * K;
+
+    const Workspace lay = workspace_layout(h, batch, J, K, s_max);
+    int rc = ensure_workspace(h, lay.total);
+    if (rc != KERDOCK_OK) return rc;
+    char *ws = reinterpret_cast<char *>(h->ws);
+    uint32_t *samples = reinterpret_cast<uint32_t *>(ws + lay.samples);
+    float *coef = reinterpret_cast<float *>(ws + lay.coef);
+    float *partial = reinterpret_cast<float *>(ws + lay.partial);
+    int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
+    int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
+    const int chunk = gather_chunk(J);
+    const int cpb = (J + chunk - 1) / chunk;
+
+    rc = launch_sample_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, samples, coef, s);
+    if (rc == KERDOCK_OK)
+        rc = launch_gather(h->dtype, h->table, h->pitch, samples, coef, batch, N, J, K, chunk,
+                           gather_unroll(), partial, s);
+    if (rc == KERDOCK_OK)
+        rc = launch_select(partial, batch, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau,
+                           p->dbg_mu, surv, nsurv, s);
+    if (rc == KERDOCK_OK)
+        rc = launch_survivors(h->A, h->n, X, batch, surv, nsurv, s_max, eps, out_idx, out_val,
+                              out_cnt, p->dbg_values, s);
+    if (rc != KERDOCK_OK) return rc;
+    if (p->dbg_samples)
+        KD_HIP(hipMemcpyAsync(p->dbg_samples, samples, (size_t)batch * N * 4, hipMemcpyDeviceToDevice, s));
+    if (p->dbg_coef)
+        KD_HIP(hipMemcpyAsync(p->dbg_coef, coef, (size_t)batch * N * 4, hipMemcpyDeviceToDevice, s));
+    if (p->dbg_survivors)
+        KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
+    return KERDOCK_OK;
+}
+
+int kerdock_query(kerdock_handle h, kerdock_info *info) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!info) return fail(KERDOCK_ERR_INVALID_ARG, "info is NULL");
+    info->m = h->m;
+    info->n = h->n;
+    info->k = h->k;
+    info->d = h->d;
+    info->L = h->L;
+    info->pitch = h->pitch;
+    info->field_poly = h->poly;
+    info->dtype = h->dtype;
+    info->table_bytes = h->table_bytes;
+    return KERDOCK_OK;
+}
+
+int kerdock_read_columns(kerdock_handle h, const uint32_t *ells, int count, float *out, void *stream) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (count < 0 || (count > 0 && (!ells || !out))) return fail(KERDOCK_ERR_INVALID_ARG, "bad arguments");
+    return launch_read_columns(h->dtype, h->table, h->m, h->pitch, h->L, h->scales, ells, count, out,
+                               reinterpret_cast<hipStream_t>(stream));
+}
+
+int kerdock_debug_signs(kerdock_handle h, int b, uint32_t *out_bits) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (b < 0 || b >= h->d / 2 || !out_bits) return fail(KERDOCK_ERR_INVALID_ARG, "bad basis or pointer");
+    const size_t wpb = h->d >= 32 ? (size_t)h->d / 32 : 1;
+    KD_HIP(hipMemcpy(out_bits, h->signs + (size_t)b * wpb, wpb * 4, hipMemcpyDeviceToHost));
+    return KERDOCK_OK;
+}
+
+int kerdock_row_scales(kerdock_handle h, float *out, void *stream) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!out) return fail(KERDOCK_ERR_INVALID_ARG, "out is NULL");
+    KD_HIP(hipMemcpyAsync(out, h->scales, (size_t)h->m * 4, hipMemcpyDeviceToDevice,
+                          reinterpret_cast<hipStream_t>(stream)));
+    return KERDOCK_OK;
+}
+
+int kerdock_destroy(kerdock_handle h) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    free_handle(h);
+    return KERDOCK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Preprocessing kernels (Algorithm 1 preprocessing step, Lemma 8) for gfx950.
+//
+// For every Kerdock basis b < d/2 and row i of A the table holds the
+// unnormalised Walsh-Hadamard transform of the signed, zero-padded row:
+//   T[b d + w][i] = sum_{x < n} A[i][x] (-1)^{Q_b(x)} (-1)^{popcount(x & w)},
+// which equals (A sqrt(d) Pi u_{M_b, w})_i because sqrt(d) 2^{-k/2} = 1
+// (equation (3) and the proof of Lemma 8: columns of A sqrt(d) Pi D_M H^k).
+// The identity block b = d/2 holds sqrt(d) A e_w (zero for w >= n).
+//
+// Layout in HBM: column l = b d + w is `pitch` contiguous elements (rows
+// i = 0..pitch-1, rows >= m are zero), so that the streaming step reads one
+// contiguous column per draw.
+#include "common.hpp"
+
+namespace kd {
+
+// ------------------------------------------------------------------ signs --
+// Bit x mod 32 of word x/32 of basis b is Q_b(x) = sum_{i<j} M_ij x_i x_j,
+// evaluated as parity( sum_{i : x_i = 1} popcount(x & U_b[i]) ) where U_b[i]
+// holds the strict upper triangle of row i.
+__global__ void k_signs(const uint16_t *__restrict__ masks, int k, int words_per_basis,
+                        int nbases, uint32_t *__restrict__ signs) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= nbases * words_per_basis) return;
+    const int b = gid / words_per_basis;
+    const int word = gid % words_per_basis;
+    uint32_t U[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) U[i] = (i < k) ? masks[b * k + i] : 0u;
+    uint32_t bits = 0;
+    const int d = 1 << k;
+    for (int q = 0; q < 32; ++q) {
+        const uint32_t x = (uint32_t)(word * 32 + q);
+        if ((int)x >= d) break;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if ((x >> i) & 1u) acc += __popc(x & U[i]);
+        bits |= (acc & 1u) << q;
+    }
+    signs[gid] = bits;
+}
+
+// ------------------------------------------------------------- row scales --
+// FP8 tables: scale_i = max(|a_i|_1, sqrt(d) |a_i|_inf) / 448 bounds every
+// |T[l]_i| (a Kerdock entry is a signed sum of a_i, an identity entry is
+// sqrt(d) a_i[w]), so a single pass can quantise.  Other dtypes: 1.
+__global__ void k_row_scales(const float *__restrict__ A, int m, int n, int pitch, float sqrt_d,
+                             int fp8, float *__restrict__ scales) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= pitch) return;
+    float l1 = 0.f, linf = 0.f;
+    if (row < m) {
+        for (int x = lane; x < n; x += 64) {
+            float a = fabsf(A[(size_t)row * n + x]);
+            l1 += a;
+            linf = fmaxf(linf, a);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        l1 += __shfl_xor(l1, off);
+        linf = fmaxf(linf, __shfl_xor(linf, off));
+    }
+    if (lane == 0) {
+        float s = 1.0f;
+        if (fp8 && row < m) {
+            float bound = fmaxf(l1, sqrt_d * linf) / 448.0f;
+            s = bound > 0.f ? bound : 1.0f;
+        }
+        scales[row] = s;
+    }
+}
+
+// --------------------------------------------------------- element stores --
+
+template <int DT> struct Store;
+template <> struct Store<KERDOCK_F32> {
+    static constexpr int ROWS = 1;   // rows packed per 32-bit store
+    __device__ static uint32_t pack(const float *v) { return __float_as_uint(v[0]); }
+};
+template <> struct Store<KERDOCK_BF16> {
+    static constexpr int ROWS = 2;
+    __device__ static uint32_t pack(const float *v) {
+        return (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+    }
+};
+template <> struct Store<KERDOCK_FP8E4M3> {
+    static constexpr int ROWS = 4;
+    __device__ static uint32_t pack(const float *v) {
+        return (uint32_t)f32_to_e4m3_sat(v[0]) | ((uint32_t)f32_to_e4m3_sat(v[1]) << 8) |
+               ((uint32_t)f32_to_e4m3_sat(v[2]) << 16) | ((uint32_t)f32_to_e4m3_sat(v[3]) << 24);
+    }
+};
+
+// ------------------------------------------------------ cross-lane moves --
+// value of v in lane (lane ^ H)
+template <int H> __device__ __forceinline__ float lane_xor(float v) {
+    if constexpr (H < 32) {
+        // ds_swizzle bitmask mode: and_mask 0x1f, or_mask 0, xor_mask H
+        return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), (H << 10) | 0x1f));
+    } else {
+        return __shfl_xor(v, 32);
+    }
+}
+
+// ----------------------------------------------------------- table build --
+// One workgroup = 16 waves = 16 consecutive rows of A and one Kerdock basis.
+// Wave r transforms row i0 + r: lane l holds elements x = q*64 + l (q < R),
+// the transform runs over the register index (bits 6..k-1) in registers and
+// over the lane index (bits 0..5) with cross-lane swizzles.  The d outputs of
+// the 16 rows are then staged, 1024 columns at a time, in LDS as [w][16 rows]
+// and written as contiguous 16-row segments of each column.  Workgroups that
+// run on the same XCD handle adjacent row strips of the same basis, so that
+// the segments of one column are merged in that XCD's L2 before reaching HBM.
+constexpr int BUILD_ROWS = 16;
+constexpr int BUILD_THREADS = BUILD_ROWS * 64;
+constexpr int STAGE_COLS = 1024;
+constexpr int STAGE_PITCH = BUILD_ROWS + 1;   // +1 float: conflict-free staging
+
+template <int LOGD> __device__ __forceinline__ void fwht_wave(float *v) {
+    constexpr int D = 1 << LOGD;
+    constexpr int R = D >= 64 ? D / 64 : 1;
+    const int lane = threadIdx.x & 63;
+    // register bits
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (q & h) continue;
+            float a = v[q], b = v[q + h];
+            v[q] = a + b;
+            v[q + h] = a - b;
+        }
+    }
+    // lane bits
+#define KD_LANE_STAGE(H)                                                    \
+    if constexpr ((H) < D) {                                                \
+        const bool upper = (lane & (H)) != 0;                               \
+        _Pragma("unroll") for (int q = 0; q < R; ++q) {                     \
+            float p = lane_xor<(H)>(v[q]);                                  \
+            v[q] = upper ? (p - v[q]) : (v[q] + p);                         \
+        }                                                                   \
+    }
+    KD_LANE_STAGE(1)
+    KD_LANE_STAGE(2)
+    KD_LANE_STAGE(4)
+    KD_LANE_STAGE(8)
+    KD_LANE_STAGE(16)
+    KD_LANE_STAGE(32)
+#undef KD_LANE_STAGE
+}
+
+template <int LOGD, int DT>
+__global__ __launch_bounds__(BUILD_THREADS) void k_table_build(
+    const float *__restrict__ A, int m, int n, int pitch, const uint32_t *__restrict__ signs,
+    const float *__restrict__ scales, void *__restrict__ table, int strips, int xcd_map) {
+    constexpr int D = 1 << LOGD;
+    constexpr int R = D >= 64 ? D / 64 : 1;
+    constexpr int WORDS = D >= 32 ? D / 32 : 1;
+    constexpr int COLS = D < STAGE_COLS ? D : STAGE_COLS;
+    __shared__ float stage[COLS * STAGE_PITCH];
+    __shared__ uint32_t sbits[WORDS];
+
+    // workgroup -> (basis, strip)
+    int g = blockIdx.x, b, strip;
+    if (xcd_map) {
+        const int per_xcd = strips / 8;
+        const int xcd = g & 7, q = g >> 3;
+        strip = xcd * per_xcd + q % per_xcd;
+        b = q / per_xcd;
+    } else {
+        strip = g % strips;
+        b = g / strips;
+    }
+    const int i0 = strip * BUILD_ROWS;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = i0 + wave;
+
+    for (int t = threadIdx.x; t < WORDS; t += BUILD_THREADS) sbits[t] = signs[(size_t)b * WORDS + t];
+    __syncthreads();
+
+    // load the signed, zero-padded row: element x = q*64 + lane
+    float v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int x = q * 64 + lane;
+        const bool live = D >= 64 || lane < D;
+        float a = 0.f;
+        if (live && row < m && x < n) a = A[(size_t)row * n + x];
+        const uint32_t bit = live ? (sbits[x >> 5] >> (x & 31)) & 1u : 0u;
+        v[q] = bit ? -a : a;
+    }
+    fwht_wave<LOGD>(v);
+
+    using S = Store<DT>;
+    constexpr int ROWS = S::ROWS;
+    constexpr int THREADS_PER_COL = BUILD_ROWS / ROWS;
+    constexpr int COLS_PER_PASS = BUILD_THREADS / THREADS_PER_COL;
+    float scale[ROWS];
+    const int my_rows = (threadIdx.x % THREADS_PER_COL) * ROWS;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) scale[r] = scales[i0 + my_rows + r];
+
+    uint32_t *out32 = reinterpret_cast<uint32_t *>(table);
+    const size_t col_words = (size_t)pitch * (DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1) / 4;
+
+#pragma unroll
+    for (int c0 = 0; c0 < D; c0 += COLS) {
+        // stage columns [c0, c0 + COLS) of this wave's row
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int w = q * 64 + lane;
+            if (w >= c0 && w < c0 + COLS && (D >= 64 || lane < D))
+                stage[(w - c0) * STAGE_PITCH + wave] = v[q];
+        }
+        __syncthreads();
+        for (int cc = threadIdx.x / THREADS_PER_COL; cc < COLS; cc += COLS_PER_PASS) {
+            float vals[ROWS];
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) vals[r] = stage[cc * STAGE_PITCH + my_rows + r] / scale[r];
+            const size_t col = (size_t)b * D + c0 + cc;
+            const size_t word = col * col_words + (size_t)(i0 + my_rows) / ROWS;
+            out32[word] = S::pack(vals);
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- identity block --
+// T[(d/2) d + w][i] = sqrt(d) A[i][w] for w < n, 0 for n <= w < d: a scaled
+// transpose through a 64 x 64 LDS tile.
+template <int DT>
+__global__ __launch_bounds__(256) void k_identity_block(const float *__restrict__ A, int m, int n,
+                                                        int d, int pitch, float sqrt_d,
+                                                        const float *__restrict__ scales,
+                                                        void *__restrict__ table) {
+    __shared__ float tile[64][65];
+    const int w0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int r = ty; r < 64; r += 4) {
+        const int i = i0 + r, w = w0 + tx;
+        tile[r][tx] = (i < m && w < n) ? sqrt_d * A[(size_t)i * n + w] : 0.f;
+    }
+    __syncthreads();
+    using S = Store<DT>;
+    constexpr int ROWS = S::ROWS;
+    constexpr int TPC = 64 / ROWS;                 // threads per column segment
+    uint32_t *out32 = reinterpret_cast<uint32_t *>(table);
+    const size_t col_words = (size_t)pitch * (DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1) / 4;
+    const size_t base_col = (size_t)(d / 2) * d;
+    for (int t = threadIdx.x; t < 64 * TPC; t += 256) {
+        const int c = t / TPC, part = t % TPC;
+        const int w = w0 + c;
+        if (w >= d) continue;
+        float vals[ROWS];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int ii = part * ROWS + r;
+            vals[r] = tile[ii][c] / scales[i0 + ii];
+        }
+        out32[(base_col + w) * col_words + (size_t)(i0 + part * ROWS) / ROWS] = S::pack(vals);
+    }
+}
+
+// ------------------------------------------------------------ read back --
+template <int DT>
+__global__ void k_read_columns(const void *__restrict__ table, int m, int pitch, int64_t L,
+                               const float *__restrict__ scales, const uint32_t *__restrict__ ells,
+                               int count, float *__restrict__ out) {
+    const int c = blockIdx.y;
+    if (c >= count) return;
+    const size_t col = ells[c];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+        float v;
+        if ((int64_t)col >= L) {
+            v = __builtin_nanf("");                // index outside the design
+        } else if constexpr (DT == KERDOCK_F32) {
+            v = reinterpret_cast<const float *>(table)[col * pitch + i];
+        } else if constexpr (DT == KERDOCK_BF16) {
+            v = bf16_to_f32(reinterpret_cast<const uint16_t *>(table)[col * pitch + i]);
+        } else {
+            v = e4m3_to_f32(reinterpret_cast<const uint8_t *>(table)[col * pitch + i]) * scales[i];
+        }
+        out[(size_t)c * m + i] = v;
+    }
+}
+
+// -------------------------------------------------------------- launchers --
+
+int launch_signs(const uint16_t *masks, int k, uint32_t *signs, hipStream_t s) {
+    const int d = 1 << k;
+    const int wpb = d >= 32 ? d / 32 : 1, nb = d / 2;
+    const int total = wpb * nb;
+    hipLaunchKernelGGL(k_signs, dim3((total + 255) / 256), dim3(256), 0, s, masks, k, wpb, nb, signs);
+    KD_LAUNCH("k_signs");
+    return KERDOCK_OK;
+}
+
+int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dtype dt,
+                      float *scales, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_scales, dim3((pitch + 3) / 4), dim3(256), 0, s, A, m, n, pitch,
+                       sqrtf((float)d), dt == KERDOCK_FP8E4M3 ? 1 : 0, scales);
+    KD_LAUNCH("k_row_scales");
+    return KERDOCK_OK;
+}
+
+template <int LOGD, int DT>
+static int build_kd(const float *A, int m, int n, int pitch, const uint32_t *signs,
+                    const float *scales, void *table, hipStream_t s) {
+    const int strips = pitch / BUILD_ROWS;
+    const int nb = (1 << LOGD) / 2;
+    const int xcd_map = (strips % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_table_build<LOGD, DT>), dim3(strips * nb), dim3(BUILD_THREADS), 0, s, A,
+                       m, n, pitch, signs, scales, table, strips, xcd_map);
+    KD_LAUNCH("k_table_build");
+    return KERDOCK_OK;
+}
+
+template <int DT>
+static int build_dt(int k, const float *A, int m, int n, int pitch, const uint32_t *signs,
+                    const float *scales, void *table, hipStream_t s) {
+    switch (k) {
+    case 2: return build_kd<2, DT>(A, m, n, pitch, signs, scales, table, s);
+    case 4: return build_kd<4, DT>(A, m, n, pitch, signs, scales, table, s);
+    case 6: return build_kd<6, DT>(A, m, n, pitch, signs, scales, table, s);
+    case 8: return build_kd<8, DT>(A, m, n, pitch, signs, scales, table, s);
+    case 10: return build_kd<10, DT>(A, m, n, pitch, signs, scales, table, s);
+    case 12: return build_kd<12, DT>(A, m, n, pitch, signs, scales, table, s);
+    default: return fail(KERDOCK_ERR_UNSUPPORTED_N, "table build: unsupported k");
+    }
+}
+
+template <int DT>
+static int identity_dt(const float *A, int m, int n, int d, int pitch, const float *scales,
+                       void *table, hipStream_t s) {
+    hipLaunchKernelGGL(k_identity_block<DT>, dim3((d + 63) / 64, pitch / 64), dim3(256), 0, s, A, m,
+                       n, d, pitch, sqrtf((float)d), scales, table);
+    KD_LAUNCH("k_identity_block");
+    return KERDOCK_OK;
+}
+
+int launch_table_build(kerdock_dtype dt, int k, const float *A, int m, int n, int pitch,
+                       const uint32_t *signs, const float *scales, void *table, hipStream_t s) {
+    const int d = 1 << k;
+    int rc;
+    switch (dt) {
+    case KERDOCK_F32:
+        rc = build_dt<KERDOCK_F32>(k, A, m, n, pitch, signs, scales, table, s);
+        if (rc == KERDOCK_OK) rc = identity_dt<KERDOCK_F32>(A, m, n, d, pitch, scales, table, s);
+        return rc;
+    case KERDOCK_BF16:
+        rc = build_dt<KERDOCK_BF16>(k, A, m, n, pitch, signs, scales, table, s);
+        if (rc == KERDOCK_OK) rc = identity_dt<KERDOCK_BF16>(A, m, n, d, pitch, scales, table, s);
+        return rc;
+    case KERDOCK_FP8E4M3:
+        rc = build_dt<KERDOCK_FP8E4M3>(k, A, m, n, pitch, signs, scales, table, s);
+        if (rc == KERDOCK_OK) rc = identity_dt<KERDOCK_FP8E4M3>(A, m, n, d, pitch, scales, table, s);
+        return rc;
+    }
+    return fail(KERDOCK_ERR_INVALID_ARG, "table build: unknown dtype");
+}
+
+int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, int64_t L,
+                        const float *scales, const uint32_t *ells, int count, float *out,
+                        hipStream_t s) {
+    if (count <= 0) return KERDOCK_OK;
+    dim3 grid((m + 255) / 256, count);
+    switch (dt) {
+    case KERDOCK_F32:
+        hipLaunchKernelGGL(k_read_columns<KERDOCK_F32>, grid, dim3(256), 0, s, table, m, pitch, L, scales, ells, count, out);
+        break;
+    case KERDOCK_BF16:
+        hipLaunchKernelGGL(k_read_columns<KERDOCK_BF16>, grid, dim3(256), 0, s, table, m, pitch, L, scales, ells, count, out);
+        break;
+    case KERDOCK_FP8E4M3:
+        hipLaunchKernelGGL(k_read_columns<KERDOCK_FP8E4M3>, grid, dim3(256), 0, s, table, m, pitch, L, scales, ells, count, out);
+        break;
+    }
+    KD_LAUNCH("k_read_columns");
+    return KERDOCK_OK;
+}
+
+}  // namespace kd

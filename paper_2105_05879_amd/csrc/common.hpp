@@ -1,0 +1,107 @@
+// Shared definitions of the gfx950 Kerdock library: table element codecs,
+// launch-error plumbing and the handle layout.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/kerdock.h"
+
+namespace kd {
+
+// ---------------------------------------------------------------- errors --
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define KD_HIP(call)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) return ::kd::hip_fail(e_, #call);             \
+    } while (0)
+
+#define KD_LAUNCH(what)                                                     \
+    do {                                                                    \
+        hipError_t e_ = hipGetLastError();                                  \
+        if (e_ != hipSuccess) return ::kd::hip_fail(e_, what);              \
+    } while (0)
+
+// ------------------------------------------------------------ geometry --
+
+// Table columns are stored with a pitch rounded up to 64 elements so that
+// every column starts on a 64-byte boundary for every element type.
+inline int column_pitch(int m) { return (m + 63) & ~63; }
+
+inline size_t dtype_bytes(kerdock_dtype t) {
+    return t == KERDOCK_F32 ? 4 : (t == KERDOCK_BF16 ? 2 : 1);
+}
+
+// -------------------------------------------------------- element codecs --
+
+// bfloat16: the upper half of an FP32 word, rounded to nearest even.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t h16) {
+    return __uint_as_float(h16 << 16);
+}
+
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, largest finite 448, no infinity):
+// round to nearest even, saturate to +-448.  The quantum of |v| in
+// [2^e, 2^(e+1)) is 2^(e-3) (e >= -6); below 2^-6 the quantum is 2^-9.
+__device__ __forceinline__ uint8_t f32_to_e4m3_sat(float v) {
+    uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+    float a = fabsf(v);
+    if (!(a < 464.0f)) return (uint8_t)(sign | 0x7Eu);   // >= 464 (and NaN) -> 448
+    int e = (int)((__float_as_uint(a) >> 23) & 0xFF) - 127;
+    if (e < -6) e = -6;
+    float q = __uint_as_float((uint32_t)(e - 3 + 127) << 23);   // 2^(e-3), exact
+    float r = rintf(a / q) * q;                                  // RNE, exact
+    if (r >= 448.0f) return (uint8_t)(sign | 0x7Eu);
+    uint32_t rb = __float_as_uint(r);
+    int re = (int)((rb >> 23) & 0xFF) - 127;
+    if (r == 0.0f) return (uint8_t)sign;
+    if (re < -6) {                                      // subnormal: r = mant * 2^-9
+        uint32_t mant = (uint32_t)(r * 512.0f);
+        return (uint8_t)(sign | mant);
+    }
+    uint32_t mant = (rb >> 20) & 0x7u;
+    return (uint8_t)(sign | ((uint32_t)(re + 7) << 3) | mant);
+}
+
+// E4M3 byte -> FP32.  Normal codes: move exponent and mantissa into an FP32
+// word and add 120 to the exponent (bias 127 - 7).  Subnormal codes (exponent
+// field 0): mantissa * 2^-9.  No FP32 denormal is ever formed.
+__device__ __forceinline__ float e4m3_to_f32(uint32_t byte) {
+    uint32_t em = byte & 0x7Fu;
+    float normal = __uint_as_float((em << 20) + (120u << 23));
+    float sub = (float)em * 0.001953125f;                       // 2^-9
+    float mag = (em >= 8u) ? normal : sub;
+    return (byte & 0x80u) ? -mag : mag;
+}
+
+}  // namespace kd
+
+// --------------------------------------------------------------- handle --
+
+struct kerdock_handle_s {
+    int m = 0, n = 0, k = 0, d = 0, pitch = 0;
+    int64_t L = 0;
+    uint32_t poly = 0;
+    kerdock_dtype dtype = KERDOCK_F32;
+    int device = 0;
+    void *table = nullptr;        // [L][pitch] elements of dtype
+    size_t table_bytes = 0;
+    float *scales = nullptr;      // [pitch] row scales (1 unless FP8)
+    float *A = nullptr;           // [m][n] copy of A
+    uint32_t *signs = nullptr;    // [d/2][d/32] sign bitmaps of the Kerdock bases
+    uint16_t *masks = nullptr;    // [d/2][k] strict-upper-triangle row masks
+    void *ws = nullptr;           // growable workspace of the streaming step
+    size_t ws_bytes = 0;
+};

@@ -1,0 +1,208 @@
+"""Python binding of the gfx950 Kerdock library (``libkerdock.so``).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels behind the C ABI declared in ``include/kerdock.h``.  The functions
+keep the C names.  Tensors must be contiguous CUDA (HIP) tensors of the
+documented dtype on the current device; streams default to torch's current
+stream.  There is no CPU fallback: without the built library every call
+raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkerdock.so")
+
+KERDOCK_F32, KERDOCK_BF16, KERDOCK_FP8E4M3 = 0, 1, 2
+DTYPES = {"f32": KERDOCK_F32, "fp32": KERDOCK_F32, "bf16": KERDOCK_BF16,
+          "fp8": KERDOCK_FP8E4M3, "fp8e4m3": KERDOCK_FP8E4M3}
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "UNSUPPORTED_N", -3: "OOM", -4: "HIP", -5: "NOT_PREPARED"}
+
+
+class KerdockError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class ApplyParams(ctypes.Structure):
+    _fields_ = [("J", ctypes.c_int32), ("K", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("t0", ctypes.c_int64), ("tau", ctypes.c_float),
+                ("dbg_samples", ctypes.c_void_p), ("dbg_coef", ctypes.c_void_p),
+                ("dbg_mu", ctypes.c_void_p), ("dbg_survivors", ctypes.c_void_p),
+                ("dbg_values", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("L", ctypes.c_int64), ("pitch", ctypes.c_int32),
+                ("field_poly", ctypes.c_uint32), ("dtype", ctypes.c_int),
+                ("table_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = {
+    "kerdock_prepare": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "kerdock_sparse_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_float, ctypes.c_int,
+                                            ctypes.POINTER(ApplyParams), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int]),
+    "kerdock_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "kerdock_read_columns": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_debug_signs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "kerdock_row_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kerdock_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libkerdock.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkerdock.so is not built: run paper_2105_05879_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise KerdockError(rc, lib().kerdock_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError("%s must be a contiguous CUDA tensor of dtype %s" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Handle:
+    """A prepared matrix: owns the device tables until destroyed."""
+
+    def __init__(self, ptr, info):
+        self.ptr = ptr
+        self.info = info
+
+    @property
+    def m(self):
+        return self.info.m
+
+    @property
+    def n(self):
+        return self.info.n
+
+    @property
+    def L(self):
+        return self.info.L
+
+    def destroy(self):
+        if self.ptr:
+            _check(lib().kerdock_destroy(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def kerdock_prepare(A, dtype="f32", stream=None):
+    """Build the Kerdock sketch tables of A (m x n FP32 CUDA tensor)."""
+    A = A if isinstance(A, torch.Tensor) else torch.as_tensor(A)
+    m, n = A.shape
+    out = ctypes.c_void_p()
+    _check(lib().kerdock_prepare(_dev(A, torch.float32, "A"), m, n, DTYPES.get(dtype, dtype),
+                                 _stream(stream), ctypes.byref(out)))
+    return Handle(out, kerdock_query(out))
+
+
+def kerdock_query(h):
+    ptr = h.ptr if isinstance(h, Handle) else h
+    info = Info()
+    _check(lib().kerdock_query(ptr, ctypes.byref(info)))
+    return info
+
+
+def kerdock_reserve(h, batch, J, K, s_max):
+    _check(lib().kerdock_reserve(h.ptr, batch, J, K, s_max))
+
+
+def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
+                         stream=None):
+    """h_eps(Ax) on the s_max rows of largest median-of-means estimate.
+
+    Returns (idx [B, s_max] int32, val [B, s_max] f32, cnt [B] int32) and,
+    with debug=True, a dict of samples, coef, mu, survivors, values."""
+    B = X.shape[0]
+    dev = X.device
+    if out is None:
+        out = (torch.empty((B, s_max), dtype=torch.int32, device=dev),
+               torch.empty((B, s_max), dtype=torch.float32, device=dev),
+               torch.empty((B,), dtype=torch.int32, device=dev))
+    idx, val, cnt = out
+    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau)
+    dbg = None
+    if debug:
+        N = J * K
+        dbg = {"samples": torch.empty((B, N), dtype=torch.int32, device=dev),
+               "coef": torch.empty((B, N), dtype=torch.float32, device=dev),
+               "mu": torch.empty((B, h.m), dtype=torch.float32, device=dev),
+               "survivors": torch.empty((B, s_max), dtype=torch.int32, device=dev),
+               "values": torch.empty((B, s_max), dtype=torch.float32, device=dev)}
+        p.dbg_samples = dbg["samples"].data_ptr()
+        p.dbg_coef = dbg["coef"].data_ptr()
+        p.dbg_mu = dbg["mu"].data_ptr()
+        p.dbg_survivors = dbg["survivors"].data_ptr()
+        p.dbg_values = dbg["values"].data_ptr()
+    _check(lib().kerdock_sparse_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max,
+                                      ctypes.byref(p), _dev(idx, torch.int32, "idx"),
+                                      _dev(val, torch.float32, "val"), _dev(cnt, torch.int32, "cnt"),
+                                      _stream(stream)))
+    if debug:
+        return idx, val, cnt, dbg
+    return idx, val, cnt
+
+
+def kerdock_read_columns(h, ells, stream=None):
+    """Dequantised table columns T[l] (times the FP8 row scale), [count, m]."""
+    ells = ells.to(torch.int32).contiguous()
+    out = torch.empty((ells.numel(), h.m), dtype=torch.float32, device=ells.device)
+    _check(lib().kerdock_read_columns(h.ptr, _ptr(ells), ells.numel(), _ptr(out), _stream(stream)))
+    return out
+
+
+def kerdock_debug_signs(h, b):
+    words = max(1, h.info.d // 32)
+    buf = (ctypes.c_uint32 * words)()
+    _check(lib().kerdock_debug_signs(h.ptr, b, buf))
+    return list(buf)
+
+
+def kerdock_row_scales(h, stream=None):
+    out = torch.empty((h.m,), dtype=torch.float32, device="cuda")
+    _check(lib().kerdock_row_scales(h.ptr, _ptr(out), _stream(stream)))
+    return out

@@ -1,0 +1,68 @@
+"""Shared helpers of the GPU parity tests: tolerances derived from the FP32
+arithmetic of each kernel, and the near-tie rule for row selections."""
+import numpy as np
+import pytest
+
+U32 = 2.0 ** -24
+
+
+def need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2105_05879_amd import kerdock
+    kerdock.lib()          # raises when the HIP library is missing
+    return kerdock
+
+
+def table_tol(A64, k):
+    """|T32 - T| for a Kerdock entry: k butterfly levels, each adding one
+    rounding of a partial sum bounded by sum_x |a_ix|."""
+    return (k + 1) * U32 * np.abs(A64).sum(1) * 1.01 + 1e-30
+
+
+def coef_tol(x64, n):
+    """c = s^T x on the GPU: 32 (64 for n > 2048) sequential adds per lane and
+    a 6-level cross-lane tree."""
+    P = 1 if n <= 2048 else 2
+    return (32 * P + 6 + 2) * U32 * np.abs(x64).sum()
+
+
+def quant_interval_check(orc, gpu, lo, hi, mode, scale=None):
+    """The GPU code is valid iff it is the rounding of some value in [lo, hi]
+    (rounding is monotone, so it must lie between the roundings of the ends)."""
+    if mode == "bf16":
+        qlo, qhi = orc.quant_bf16(lo), orc.quant_bf16(hi)
+    else:
+        qlo, qhi = orc.quant_e4m3(lo / scale) * scale, orc.quant_e4m3(hi / scale) * scale
+    return (gpu >= np.minimum(qlo, qhi) - 1e-30 * np.abs(qlo)) & (gpu <= np.maximum(qlo, qhi) + 1e-30 * np.abs(qhi))
+
+
+def mu_tolerance(cols, coef, J, K, tolT, tolc, chunk):
+    """Bound on |mu_gpu - mu_oracle| per row from the per-draw errors of the
+    table entries (tolT, per draw and row) and coefficients (tolc, per draw), plus the
+    FP32 accumulation over at most `chunk` FMAs and J/chunk partial sums.
+    The median is 1-Lipschitz in the max norm, so the batch bound carries over."""
+    N = J * K
+    ac = np.abs(coef)[:, None]
+    aT = np.abs(cols)
+    per = ac * tolT + aT * tolc[:, None] + (min(chunk, J) + J // max(1, chunk) + 4) * U32 * ac * aT
+    per = per.reshape(K, J, -1).sum(1) / J
+    return per.max(0) + 4 * U32 * np.abs((cols * coef[:, None]).reshape(K, J, -1).sum(1) / J).max(0)
+
+
+def check_selection(mu_orc, mu_tol, gpu_set, s_max, tau=0.0):
+    """S_gpu must equal the oracle's top-s_max by |mu| (ties: smaller index),
+    except for rows whose oracle |mu| lies within the tolerance of the s_max-th
+    largest value (an FP32 near-tie).  Returns the number of admitted
+    exceptions; fails on any other difference."""
+    m = mu_orc.size
+    a = np.abs(mu_orc)
+    order = np.lexsort((np.arange(m), -a))
+    orc_set = set(order[:s_max][a[order[:s_max]] >= tau].tolist())
+    theta = a[order[min(s_max, m) - 1]]
+    diff = orc_set.symmetric_difference(set(gpu_set))
+    for i in diff:
+        assert abs(a[i] - theta) <= mu_tol[i] + mu_tol.max() + 1e-12, \
+            "row %d: |mu| %.9g vs cut %.9g (tol %.3g)" % (i, a[i], theta, mu_tol[i])
+    return len(diff)

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bit-exact: sign patterns, drawn design indices.  Within derived FP32 bounds:
+table entries (FWHT rounding), coefficients, median-of-means estimates.
+Selections: identical up to FP32 near-ties at the s_max-th value.  Survivor
+values: 1e-5 relative (compensated dot product from FP32 A and x)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (U32, check_selection, coef_tol, mu_tolerance, need_gpu,
+                        quant_interval_check, table_tol)
+from paper_2105_05879_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = ["f32", "bf16", "fp8"]
+
+
+def rand_A(m, n, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((m, n)) / np.sqrt(n)).astype(np.float32)
+
+
+def unit_rows(B, n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((B, n))
+    return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+
+
+def prepare(kd, A, dtype):
+    return kd.kerdock_prepare(torch.from_numpy(A).cuda(), dtype)
+
+
+def orc_scales(A64, d):
+    b = np.maximum(np.abs(A64).sum(1), np.sqrt(d) * np.abs(A64).max(1)) / 448.0
+    s = b.astype(np.float32).astype(np.float64)
+    s[s == 0] = 1.0
+    return s
+
+
+def entry_tolerance(orc, ref, A64, k, d, dtype):
+    """Per-entry bound on |T_gpu - T_oracle| for the values each side uses.
+    FP32: the FWHT rounding bound.  BF16/FP8: both sides round a value in
+    [ref - e, ref + e]; they agree unless that interval straddles a rounding
+    boundary, in which case they differ by at most one quantum."""
+    tolT = np.broadcast_to(table_tol(A64, k)[None, :], ref.shape)
+    if dtype == "f32":
+        return tolT, ref
+    if dtype == "bf16":
+        lo, hi = orc.quant_bf16(ref - tolT), orc.quant_bf16(ref + tolT)
+        used = orc.quant_bf16(ref)
+    else:
+        s = orc_scales(A64, d)[None, :]
+        rel = 4 * A64.shape[1] * U32
+        lo = orc.quant_e4m3((ref - tolT) / (s * (1 + rel))) * s
+        hi = orc.quant_e4m3((ref + tolT) / (s * (1 - rel))) * s
+        lo2 = orc.quant_e4m3((ref - tolT) / (s * (1 - rel))) * s
+        hi2 = orc.quant_e4m3((ref + tolT) / (s * (1 + rel))) * s
+        lo, hi = np.minimum(lo, lo2), np.maximum(hi, hi2)
+        used = orc.quant_e4m3(ref / s) * s
+    return np.abs(hi - lo) * 1.0001 + 1e-30, used
+
+
+# --------------------------------------------------------------- signs ---
+
+@pytest.mark.parametrize("n", [1, 4, 16, 64, 256, 1024, 4096])
+def test_signs_and_field_bit_exact(orc, n):
+    kd = need_gpu()
+    h = prepare(kd, rand_A(4, n, n), "f32")
+    k = orc.choose_k(n)
+    assert h.info.k == k and h.info.d == 1 << k and h.info.L == orc.design_size(k)
+    assert h.info.field_poly == orc.field_poly(k - 1)
+    nb = (1 << k) // 2
+    bases = range(nb) if nb <= 128 else sorted(set([0, 1, nb - 1] + list(
+        np.random.default_rng(n).integers(0, nb, 61))))
+    for b in bases:
+        assert np.array_equal(np.array(kd.kerdock_debug_signs(h, b), dtype=np.uint32),
+                              orc.sign_words(k, b)), "basis %d" % b
+    h.destroy()
+
+
+# --------------------------------------------------------------- tables ---
+
+TABLE_CASES = [(1, 1), (3, 4), (16, 16), (50, 50), (64, 64), (100, 100), (300, 100), (70, 300),
+               (256, 256), (1000, 1000), (2048, 2048)]
+
+
+def pick_columns(L, d, n, count, seed):
+    rng = np.random.default_rng(seed)
+    nb = d // 2
+    fixed = [0, d - 1, d, 2 * d - 1, (nb - 1) * d, nb * d - 1, nb * d, nb * d + n - 1, L - 1]
+    if n < d:
+        fixed.append(nb * d + n)
+    cols = sorted(set([c for c in fixed if 0 <= c < L] + list(rng.integers(0, L, count))))
+    return np.array(cols, dtype=np.int64)
+
+
+@pytest.mark.parametrize("m,n", TABLE_CASES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_table_columns(orc, m, n, dtype):
+    kd = need_gpu()
+    A = rand_A(m, n, 7 * m + n)
+    A64 = A.astype(np.float64)
+    h = prepare(kd, A, dtype)
+    k, d, L = h.info.k, h.info.d, h.info.L
+    ells = pick_columns(L, d, n, 96, m + n)
+    gpu = kd.kerdock_read_columns(h, torch.from_numpy(ells.astype(np.int32)).cuda()).cpu().numpy().astype(np.float64)
+    ref = np.stack([orc.table_column(A64, l) for l in ells])
+    tolT = np.broadcast_to(table_tol(A64, k)[None, :], ref.shape)
+    if dtype == "f32":
+        bad = np.abs(gpu - ref) > tolT
+        assert not bad.any(), "max excess %g" % (np.abs(gpu - ref) - tolT).max()
+    elif dtype == "bf16":
+        assert quant_interval_check(orc, gpu, ref - tolT, ref + tolT, "bf16").all()
+    else:
+        s_orc = orc_scales(A64, d)
+        s_gpu = kd.kerdock_row_scales(h).cpu().numpy().astype(np.float64)
+        rel = 4 * n * U32
+        assert np.all(np.abs(s_gpu / s_orc - 1) <= rel)
+        q_gpu = orc.quant_e4m3(gpu / s_gpu[None, :])
+        cands = [orc.quant_e4m3(v / (s_orc[None, :] * f))
+                 for v in (ref - tolT, ref + tolT) for f in (1 - rel, 1 + rel)]
+        lo, hi = np.minimum.reduce(cands), np.maximum.reduce(cands)
+        assert np.all((q_gpu >= lo) & (q_gpu <= hi))
+        assert np.all(np.abs(q_gpu) <= 448)
+    h.destroy()
+
+
+# ------------------------------------------------------ streaming step ---
+
+APPLY_CASES = [
+    # m, n, J, K, s_max
+    (1, 1, 5, 1, 1),
+    (16, 16, 9, 3, 4),
+    (64, 64, 37, 3, 10),
+    (100, 100, 50, 2, 20),
+    (300, 100, 64, 4, 40),
+    (70, 300, 33, 5, 70),
+    (256, 256, 200, 1, 30),
+    (1000, 1000, 130, 2, 60),
+    (2048, 2048, 96, 2, 320),
+]
+
+
+def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, eps=None):
+    if m == n and n >= 64:
+        A = workloads.structured_dictionary(n, np.random.default_rng(n)).astype(np.float32)
+    else:
+        A = rand_A(m, n, m * 31 + n)
+    A64 = A.astype(np.float64)
+    X = unit_rows(B, n, m + 3 * n)
+    X64 = X.astype(np.float64)
+    if eps is None:
+        eps = float(np.quantile(np.abs(X64 @ A64.T), 0.9)) + 1e-6
+    h = prepare(kd, A, dtype)
+    idx, val, cnt, dbg = kd.kerdock_sparse_apply(h, torch.from_numpy(X).cuda(), eps, s_max, J, K,
+                                                  seed, t0=t0, tau=tau, debug=True)
+    torch.cuda.synchronize()
+    g = {key: v.cpu().numpy() for key, v in dbg.items()}
+    g.update(idx=idx.cpu().numpy(), val=val.cpu().numpy(), cnt=cnt.cpu().numpy())
+    mode = {"f32": "exact", "bf16": "bf16", "fp8": "fp8"}[dtype]
+    r = orc.sparse_apply(A64, X64, J, K, eps, s_max, seed=seed, t0=t0, tau=tau, table_mode=mode, debug=True)
+    info = h.info
+    h.destroy()
+    return A64, X64, g, r, info, eps
+
+
+def check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, tau=0.0, chunk=512):
+    k, d, n = info.k, info.d, A64.shape[1]
+    exceptions = 0
+    for t in range(X64.shape[0]):
+        # draws: bit-exact
+        assert np.array_equal(g["samples"][t].view(np.uint32).astype(np.int64), r["samples"][t])
+        # coefficients
+        ct = coef_tol(X64[t], n)
+        assert np.all(np.abs(g["coef"][t] - r["coef"][t]) <= ct), np.abs(g["coef"][t] - r["coef"][t]).max()
+        # median of means
+        ref = np.stack([orc.table_column(A64, l) for l in r["samples"][t]])
+        tolE, used = entry_tolerance(orc, ref, A64, k, d, dtype)
+        mt = mu_tolerance(used, r["coef"][t], J, K, tolE, np.full(J * K, ct), chunk)
+        dmu = np.abs(g["mu"][t] - r["mu"][t])
+        assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+        # selection
+        gs = g["survivors"][t]
+        gset = gs[gs >= 0]
+        assert np.all(np.diff(gset) > 0), "survivors not ascending"
+        exceptions += check_selection(r["mu"][t], mt, gset.tolist(), s_max, tau)
+        # survivor values: Dot2 vs FP64
+        ns = len(gset)
+        v64 = A64[gset] @ X64[t]
+        gv = g["values"][t][:ns].astype(np.float64)
+        scale = np.abs(A64[gset] * X64[t][None, :]).sum(1)
+        assert np.all(np.abs(gv - v64) <= 1e-5 * np.abs(v64) + 4 * U32 * U32 * n * scale + 1e-30)
+        assert np.all(g["values"][t][ns:] == 0)
+        # threshold
+        c = g["cnt"][t]
+        keep = gset[np.abs(gv) >= eps]
+        assert np.array_equal(g["idx"][t][:c], keep)
+        assert np.all(g["idx"][t][c:] == -1) and np.all(g["val"][t][c:] == 0)
+        assert np.array_equal(g["val"][t][:c], gv[np.abs(gv) >= eps].astype(np.float32))
+        # against the oracle's output, rows outside near-ties agree exactly
+        oc = r["out_cnt"][t]
+        o_idx, o_val = r["out_idx"][t][:oc], r["out_val"][t][:oc]
+        common = np.intersect1d(o_idx, keep)
+        surv_diff = set(np.setxor1d(gset, r["surv"][t][r["surv"][t] >= 0]).tolist())
+        for i in np.setxor1d(o_idx, keep):
+            near_eps = abs(abs(A64[i] @ X64[t]) - eps) <= 1e-5 * eps
+            assert near_eps or int(i) in surv_diff, "row %d kept by one side only" % i
+        gv_map = dict(zip(g["idx"][t][:c].tolist(), g["val"][t][:c].tolist()))
+        for i, v in zip(o_idx.tolist(), o_val.tolist()):
+            if i in gv_map:
+                assert abs(gv_map[i] - v) <= 1e-5 * abs(v)
+    return exceptions
+
+
+@pytest.mark.parametrize("m,n,J,K,s_max", APPLY_CASES)
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_apply_parity(orc, m, n, J, K, s_max, dtype):
+    kd = need_gpu()
+    A64, X64, g, r, info, eps = run_case(orc, kd, m, n, J, K, s_max, dtype)
+    exc = check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype)
+    assert exc <= 1
+
+
+def test_apply_tau_and_take_all(orc):
+    kd = need_gpu()
+    for tau, s_max in [(0.05, 24), (0.0, 64)]:
+        A64, X64, g, r, info, eps = run_case(orc, kd, 64, 64, 40, 2, s_max, "f32", tau=tau)
+        check_case(orc, A64, X64, g, r, info, eps, 40, 2, s_max, "f32", tau=tau)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 6, 9, 16, 32])
+def test_median_all_batch_counts(orc, K):
+    kd = need_gpu()
+    A64, X64, g, r, info, eps = run_case(orc, kd, 64, 64, 7, K, 12, "f32", B=2)
+    check_case(orc, A64, X64, g, r, info, eps, 7, K, 12, "f32")
+
+
+def test_deterministic(orc):
+    kd = need_gpu()
+    A = rand_A(256, 256, 5)
+    X = torch.from_numpy(unit_rows(4, 256, 6)).cuda()
+    h = prepare(kd, A, "bf16")
+    a = kd.kerdock_sparse_apply(h, X, 0.05, 16, 300, 2, 9, debug=True)
+    b = kd.kerdock_sparse_apply(h, X, 0.05, 16, 300, 2, 9, debug=True)
+    for u, v in zip(a[:3], b[:3]):
+        assert torch.equal(u, v)
+    for key in a[3]:
+        assert torch.equal(a[3][key], b[3][key])
+    h.destroy()
+
+
+def test_stream_position(orc):
+    """Draws depend only on (seed, t0 + t, j): rows 1.. of a call with t0
+    equal rows 0.. of a call with t0 + 1."""
+    kd = need_gpu()
+    h = prepare(kd, rand_A(64, 64, 1), "f32")
+    X = torch.from_numpy(unit_rows(3, 64, 2)).cuda()
+    a = kd.kerdock_sparse_apply(h, X, 0.1, 8, 20, 2, 77, t0=100, debug=True)
+    b = kd.kerdock_sparse_apply(h, X[1:].contiguous(), 0.1, 8, 20, 2, 77, t0=101, debug=True)
+    assert torch.equal(a[3]["samples"][1:], b[3]["samples"])
+    h.destroy()
+
+
+def test_errors(orc):
+    kd = need_gpu()
+    A = torch.from_numpy(rand_A(32, 32, 1)).cuda()
+    with pytest.raises(kd.KerdockError) as e:
+        kd.kerdock_prepare(torch.zeros((4, 5000), device="cuda"))
+    assert e.value.code == -2
+    h = kd.kerdock_prepare(A)
+    X = torch.from_numpy(unit_rows(2, 32, 1)).cuda()
+    for kw, code in [(dict(eps=0.0, s_max=4, J=2, K=2), -1), (dict(eps=0.1, s_max=33, J=2, K=2), -1),
+                     (dict(eps=0.1, s_max=4, J=0, K=2), -1), (dict(eps=0.1, s_max=4, J=2, K=33), -1),
+                     (dict(eps=float("nan"), s_max=4, J=2, K=2), -1)]:
+        with pytest.raises(kd.KerdockError) as e:
+            kd.kerdock_sparse_apply(h, X, seed=0, **kw)
+        assert e.value.code == code
+    # empty batch is a no-op
+    out = kd.kerdock_sparse_apply(h, X[:0], 0.1, 4, 2, 2, 0)
+    assert out[0].shape == (0, 4)
+    h.destroy()
+
+
+def test_zero_matrix(orc):
+    kd = need_gpu()
+    h = prepare(kd, np.zeros((40, 40), dtype=np.float32), "fp8")
+    X = torch.from_numpy(unit_rows(2, 40, 3)).cuda()
+    idx, val, cnt = kd.kerdock_sparse_apply(h, X, 0.01, 5, 10, 3, 1)
+    assert cnt.sum().item() == 0 and (idx == -1).all()
+    h.destroy()
