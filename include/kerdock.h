@@ -82,6 +82,10 @@ typedef struct {
     float *dbg_mu;         /* [batch][m] median-of-means estimate             */
     int32_t *dbg_survivors;/* [batch][s_max] S ascending, -1 padded           */
     float *dbg_values;     /* [batch][s_max] a_i.x for every i in S, 0 padded */
+    /* optional host [4]: when set, the call records HIP events on `stream`
+       around its four kernels (draws + coefficients, gather, select,
+       survivor dots), waits for them and stores their durations in ms. */
+    float *kernel_ms;
 } kerdock_apply_params;
 
 /*

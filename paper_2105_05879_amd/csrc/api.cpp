@@ -116,6 +116,8 @@ static void free_handle(kerdock_handle_s *h) {
     hipFree(h->signs);
     hipFree(h->masks);
     hipFree(h->ws);
+    for (int q = 0; q < 5; ++q)
+        if (h->ev[q]) hipEventDestroy(h->ev[q]);
     delete h;
 }
 
@@ -235,17 +237,29 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     const int chunk = gather_chunk(J);
     const int cpb = (J + chunk - 1) / chunk;
 
+    const bool timed = p->kernel_ms != nullptr;
+    if (timed && !h->ev[0])
+        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
+    if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
     rc = launch_sample_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, samples, coef, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
     if (rc == KERDOCK_OK)
         rc = launch_gather(h->dtype, h->table, h->pitch, samples, coef, batch, N, J, K, chunk,
                            gather_unroll(), partial, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
     if (rc == KERDOCK_OK)
         rc = launch_select(partial, batch, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau,
                            p->dbg_mu, surv, nsurv, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
     if (rc == KERDOCK_OK)
         rc = launch_survivors(h->A, h->n, X, batch, surv, nsurv, s_max, eps, out_idx, out_val,
                               out_cnt, p->dbg_values, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;
+    if (timed) {
+        KD_HIP(hipEventSynchronize(h->ev[4]));
+        for (int q = 0; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
+    }
     if (p->dbg_samples)
         KD_HIP(hipMemcpyAsync(p->dbg_samples, samples, (size_t)batch * N * 4, hipMemcpyDeviceToDevice, s));
     if (p->dbg_coef)

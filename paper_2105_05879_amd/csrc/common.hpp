@@ -104,4 +104,5 @@ struct kerdock_handle_s {
     uint16_t *masks = nullptr;    // [d/2][k] strict-upper-triangle row masks
     void *ws = nullptr;           // growable workspace of the streaming step
     size_t ws_bytes = 0;
+    hipEvent_t ev[5] = {};        // kernel timing events (created on first use)
 };

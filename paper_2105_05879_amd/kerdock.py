@@ -32,7 +32,7 @@ class ApplyParams(ctypes.Structure):
                 ("t0", ctypes.c_int64), ("tau", ctypes.c_float),
                 ("dbg_samples", ctypes.c_void_p), ("dbg_coef", ctypes.c_void_p),
                 ("dbg_mu", ctypes.c_void_p), ("dbg_survivors", ctypes.c_void_p),
-                ("dbg_values", ctypes.c_void_p)]
+                ("dbg_values", ctypes.c_void_p), ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
 
 
 class Info(ctypes.Structure):
@@ -152,11 +152,13 @@ def kerdock_reserve(h, batch, J, K, s_max):
 
 
 def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
-                         stream=None):
+                         stream=None, kernel_ms=None):
     """h_eps(Ax) on the s_max rows of largest median-of-means estimate.
 
     Returns (idx [B, s_max] int32, val [B, s_max] f32, cnt [B] int32) and,
-    with debug=True, a dict of samples, coef, mu, survivors, values."""
+    with debug=True, a dict of samples, coef, mu, survivors, values.
+    kernel_ms: optional (ctypes.c_float * 4)() that receives the durations
+    of the four kernels, timed with HIP events on the call's stream."""
     B = X.shape[0]
     dev = X.device
     if out is None:
@@ -165,6 +167,8 @@ def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, 
                torch.empty((B,), dtype=torch.int32, device=dev))
     idx, val, cnt = out
     p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau)
+    if kernel_ms is not None:          # a ctypes c_float * 4 filled by the call
+        p.kernel_ms = ctypes.cast(kernel_ms, ctypes.POINTER(ctypes.c_float))
     dbg = None
     if debug:
         N = J * K
