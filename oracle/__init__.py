@@ -54,6 +54,7 @@ def _load():
         "ko_quant_bf16": (c_d, [c_d]),
         "ko_quant_e4m3": (c_d, [c_d]),
         "ko_sign_words": (None, [c_i, c_u64, c_p]),
+        "ko_table_entries": (None, [c_p, c_i, c_i, c_p, c_i64, c_p, c_i, c_p]),
         "ko_mu_rows": (None, [c_p, c_i, c_i, c_p, c_p, c_i, c_i, c_p, c_i, c_i, c_p]),
         "ko_sparse_apply": (c_i, [c_p, c_i, c_i, c_p, c_i, c_i64, c_u64, c_i, c_i, c_d, c_i,
                                   c_d, c_i, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
@@ -159,6 +160,17 @@ def sign_words(k, s):
     """(-1)^{Q_{M_s}(x)} for x < d as bit x mod 32 of word x // 32."""
     out = np.zeros(max(1, (1 << k) // 32), dtype=np.uint32)
     _load().ko_sign_words(int(k), int(s), _ptr(out))
+    return out
+
+
+def table_entries(A, samples, rows):
+    """T[l_j]_r for the given draws (N) and rows (R): array (N, R)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    m, n = A.shape
+    ls = np.ascontiguousarray(samples, dtype=np.int64)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    out = np.zeros((ls.size, rows.size), dtype=np.float64)
+    _load().ko_table_entries(_ptr(A), m, n, _ptr(ls), ls.size, _ptr(rows), rows.size, _ptr(out))
     return out
 
 

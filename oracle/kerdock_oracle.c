@@ -346,6 +346,26 @@ static double median_of(double *v, int K)
     return 0.5 * (v[K / 2 - 1] + v[K / 2]);
 }
 
+/* table entries T[l_j]_r = a_r . s_lj for given draws and chosen rows,
+ * out[j * nrows + r] (row-restricted sketch columns, for full-size checks) */
+void ko_table_entries(const double *A, int m, int n, const int64_t *ls, int64_t N,
+                      const int32_t *rows, int nrows, double *out)
+{
+    int k = ko_choose_k(n);
+    (void)m;
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < N; j++) {
+        double s[4096];
+        ko_design_vector(n, k, ls[j], s);
+        for (int r = 0; r < nrows; r++) {
+            const double *a = A + (size_t)rows[r] * n;
+            double acc = 0.0;
+            for (int q = 0; q < n; q++) acc += a[q] * s[q];
+            out[(size_t)j * nrows + r] = acc;
+        }
+    }
+}
+
 /*
  * The median-of-means estimate restricted to chosen rows, for one vector x
  * and given draws l_j (j < J K): mu_r = median_k (1/J) sum_{j in batch k}
@@ -361,6 +381,7 @@ void ko_mu_rows(const double *A, int m, int n, const double *x, const int64_t *l
     double *c = (double *)malloc(sizeof(double) * (size_t)N);
     double *s = (double *)malloc(sizeof(double) * (size_t)n);
     double *S = (double *)malloc(sizeof(double) * (size_t)N * n);
+    #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t j = 0; j < N; j++) {
         ko_design_vector(n, k, ls[j], S + (size_t)j * n);
         double acc = 0.0;

@@ -8,8 +8,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import (U32, check_selection, coef_tol, mu_tolerance, need_gpu,
-                        quant_interval_check, table_tol)
+from gpu_common import (U32, check_selection, coef_tol, entry_tolerance, mu_tolerance, need_gpu,
+                        orc_scales, quant_interval_check, table_tol)
 from paper_2105_05879_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -30,36 +30,6 @@ def unit_rows(B, n, seed):
 
 def prepare(kd, A, dtype):
     return kd.kerdock_prepare(torch.from_numpy(A).cuda(), dtype)
-
-
-def orc_scales(A64, d):
-    b = np.maximum(np.abs(A64).sum(1), np.sqrt(d) * np.abs(A64).max(1)) / 448.0
-    s = b.astype(np.float32).astype(np.float64)
-    s[s == 0] = 1.0
-    return s
-
-
-def entry_tolerance(orc, ref, A64, k, d, dtype):
-    """Per-entry bound on |T_gpu - T_oracle| for the values each side uses.
-    FP32: the FWHT rounding bound.  BF16/FP8: both sides round a value in
-    [ref - e, ref + e]; they agree unless that interval straddles a rounding
-    boundary, in which case they differ by at most one quantum."""
-    tolT = np.broadcast_to(table_tol(A64, k)[None, :], ref.shape)
-    if dtype == "f32":
-        return tolT, ref
-    if dtype == "bf16":
-        lo, hi = orc.quant_bf16(ref - tolT), orc.quant_bf16(ref + tolT)
-        used = orc.quant_bf16(ref)
-    else:
-        s = orc_scales(A64, d)[None, :]
-        rel = 4 * A64.shape[1] * U32
-        lo = orc.quant_e4m3((ref - tolT) / (s * (1 + rel))) * s
-        hi = orc.quant_e4m3((ref + tolT) / (s * (1 - rel))) * s
-        lo2 = orc.quant_e4m3((ref - tolT) / (s * (1 - rel))) * s
-        hi2 = orc.quant_e4m3((ref + tolT) / (s * (1 + rel))) * s
-        lo, hi = np.minimum(lo, lo2), np.maximum(hi, hi2)
-        used = orc.quant_e4m3(ref / s) * s
-    return np.abs(hi - lo) * 1.0001 + 1e-30, used
 
 
 # --------------------------------------------------------------- signs ---
