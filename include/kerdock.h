@@ -77,14 +77,17 @@ typedef struct {
                               pure function of (seed, t0 + t, j)              */
     float tau;             /* optional floor on |mu| inside S (0 = none)      */
     /* optional device outputs for parity checks (NULL = not written):       */
-    uint32_t *dbg_samples; /* [batch][N] drawn design indices l_j             */
+    uint32_t *dbg_samples; /* [batch][N] drawn design indices l_j (set together
+                              with dbg_coef)                                  */
     float *dbg_coef;       /* [batch][N] s_{l_j}^T x                          */
     float *dbg_mu;         /* [batch][m] median-of-means estimate             */
     int32_t *dbg_survivors;/* [batch][s_max] S ascending, -1 padded           */
     float *dbg_values;     /* [batch][s_max] a_i.x for every i in S, 0 padded */
     /* optional host [4]: when set, the call records HIP events on `stream`
-       around its four kernels (draws + coefficients, gather, select,
-       survivor dots), waits for them and stores their durations in ms. */
+       around its kernels, waits for them and stores their durations in ms:
+       [0] 0 (draws and coefficients run inside the gather kernel),
+       [1] draws + coefficients + gather, [2] batch means, median and
+       selection, [3] survivor dots and threshold. */
     float *kernel_ms;
 } kerdock_apply_params;
 

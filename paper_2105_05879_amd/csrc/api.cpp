@@ -23,12 +23,11 @@ int launch_table_build(kerdock_dtype dt, int k, const float *A, int m, int n, in
 int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, int64_t L,
                         const float *scales, const uint32_t *ells, int count, float *out,
                         hipStream_t s);
-int launch_sample_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs,
-                       uint64_t seed, int64_t t0, int N, uint32_t *samples, float *coef,
+int launch_draw_gather(kerdock_dtype dt, const void *table, int pitch, const float *X, int batch, int n,
+                       int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int J, int K,
+                       int chunk, int unroll, float *partial, uint32_t *dbg_samples, float *dbg_coef,
                        hipStream_t s);
-int launch_gather(kerdock_dtype dt, const void *table, int pitch, const uint32_t *samples,
-                  const float *coef, int batch, int N, int J, int K, int chunk, int unroll,
-                  float *partial, hipStream_t s);
+int gather_chunk_max();
 int launch_select(const float *partial, int batch, int m, int pitch, int K, int cpb, int J,
                   const float *scales, int s_max, float tau, float *mu_out, int32_t *surv,
                   int32_t *nsurv, hipStream_t s);
@@ -61,17 +60,15 @@ static int env_int(const char *name, int dflt) {
 static int gather_chunk(int J) {
     int c = env_int("KERDOCK_CHUNK", 512);
     if (c < 16) c = 16;
+    if (c > gather_chunk_max()) c = gather_chunk_max();
     return c < J ? c : J;
 }
 
-static int gather_unroll() {
-    int u = env_int("KERDOCK_UNROLL", 8);
-    return (u == 4 || u == 16) ? u : 8;
-}
+static int gather_unroll() { return env_int("KERDOCK_UNROLL", 8); }
 
 // workspace layout of the streaming step
 struct Workspace {
-    size_t samples, coef, partial, surv, nsurv, total;
+    size_t partial, surv, nsurv, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -82,8 +79,7 @@ static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, i
     const size_t cpb = (J + chunk - 1) / chunk;
     Workspace w;
     size_t off = 0;
-    w.samples = off; off += align256((size_t)batch * N * 4);
-    w.coef = off;    off += align256((size_t)batch * N * 4);
+    (void)N;
     w.partial = off; off += align256((size_t)batch * K * cpb * h->pitch * 4);
     w.surv = off;    off += align256((size_t)batch * s_max * 4);
     w.nsurv = off;   off += align256((size_t)batch * 4);
@@ -229,23 +225,22 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     int rc = ensure_workspace(h, lay.total);
     if (rc != KERDOCK_OK) return rc;
     char *ws = reinterpret_cast<char *>(h->ws);
-    uint32_t *samples = reinterpret_cast<uint32_t *>(ws + lay.samples);
-    float *coef = reinterpret_cast<float *>(ws + lay.coef);
     float *partial = reinterpret_cast<float *>(ws + lay.partial);
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
     const int chunk = gather_chunk(J);
     const int cpb = (J + chunk - 1) / chunk;
+    if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
+        return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
 
+    // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
+    // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
     const bool timed = p->kernel_ms != nullptr;
     if (timed && !h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
-    if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
-    rc = launch_sample_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, samples, coef, s);
-    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
-    if (rc == KERDOCK_OK)
-        rc = launch_gather(h->dtype, h->table, h->pitch, samples, coef, batch, N, J, K, chunk,
-                           gather_unroll(), partial, s);
+    if (timed) KD_HIP(hipEventRecord(h->ev[1], s));
+    rc = launch_draw_gather(h->dtype, h->table, h->pitch, X, batch, h->n, h->k, h->L, h->signs, p->seed,
+                            p->t0, J, K, chunk, gather_unroll(), partial, p->dbg_samples, p->dbg_coef, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
     if (rc == KERDOCK_OK)
         rc = launch_select(partial, batch, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau,
@@ -258,12 +253,9 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     if (rc != KERDOCK_OK) return rc;
     if (timed) {
         KD_HIP(hipEventSynchronize(h->ev[4]));
-        for (int q = 0; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
+        p->kernel_ms[0] = 0.f;
+        for (int q = 1; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
     }
-    if (p->dbg_samples)
-        KD_HIP(hipMemcpyAsync(p->dbg_samples, samples, (size_t)batch * N * 4, hipMemcpyDeviceToDevice, s));
-    if (p->dbg_coef)
-        KD_HIP(hipMemcpyAsync(p->dbg_coef, coef, (size_t)batch * N * 4, hipMemcpyDeviceToDevice, s));
     if (p->dbg_survivors)
         KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
     return KERDOCK_OK;

@@ -47,104 +47,33 @@ __device__ __forceinline__ uint32_t walsh32(uint32_t v) {
     return w;
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-// ------------------------------------------------------------ draws + c_j --
-// Draw j of vector t: block floor(j/4) of Philox4x64-10 at counter
-// (floor(j/4), t0 + t, 0, 0), key (seed, 0), word j mod 4; l = floor(r L / 2^64).
-// One wave handles 64 consecutive draws.  Lane l holds x[e] for
-// e = (l + 64 p) * 32 + q, q < 32, so that the sign word (l + 64 p) of basis b
-// carries Q_b(e) in bit q; with w = (w_hi, w_lo) the Walsh sign is
-// parity((l + 64 p) & w_hi) ^ parity(q & w_lo).
-template <int P>
-__global__ __launch_bounds__(256) void k_sample_coef(const float *__restrict__ X, int n, int k,
-                                                     int64_t L, const uint32_t *__restrict__ signs,
-                                                     uint64_t seed, int64_t t0, int N,
-                                                     uint32_t *__restrict__ samples,
-                                                     float *__restrict__ coef) {
-    const int t = blockIdx.y;
-    const int lane = threadIdx.x & 63;
-    const int j0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 64;
-    if (j0 >= N) return;
-    const int d = 1 << k;
-    const int words = d >= 32 ? d / 32 : 1;
-    const float *x = X + (size_t)t * n;
-
-    float xv[P][32];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-            const int e = (lane + 64 * p) * 32 + q;
-            xv[p][q] = e < n ? x[e] : 0.f;
-        }
-
-    uint32_t ell[4];
-    {
-        uint64_t c[4] = {(uint64_t)(j0 / 4 + lane), (uint64_t)(t0 + t), 0, 0};
-        philox4x64_10(c, seed, 0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) ell[q] = (uint32_t)__umul64hi(c[q], (uint64_t)L);
-    }
-
-    const float sqrt_d = sqrtf((float)d);
-    float my_coef = 0.f;
-    uint32_t my_ell = 0;
-    const int jcount = min(64, N - j0);
-    for (int jb = 0; jb * 4 < jcount; ++jb) {
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-            const int jj = jb * 4 + q4;
-            if (jj >= jcount) continue;
-            const uint32_t l = __builtin_amdgcn_readlane(ell[q4], jb);
-            const uint32_t b = l >> k, w = l & (uint32_t)(d - 1);
-            float c;
-            if ((int)b == d / 2) {
-                c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
-            } else {
-                const uint32_t wlo = walsh32(w & 31u);
-                float part = 0.f;
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const uint32_t word = (uint32_t)(lane + 64 * p);
-                    if ((int)word < words) {
-                        const uint32_t sw = signs[(size_t)b * words + word];
-                        const uint32_t par = __popc(word & (w >> 5)) & 1u;
-                        const uint32_t mask = sw ^ wlo ^ (0u - par);
-#pragma unroll
-                        for (int q = 0; q < 32; ++q)
-                            part += ((mask >> q) & 1u) ? -xv[p][q] : xv[p][q];
-                    }
-                }
-                c = wave_sum(part);
-            }
-            if (lane == jj) {
-                my_coef = c;
-                my_ell = l;
-            }
-        }
-    }
-    if (j0 + lane < N) {
-        samples[(size_t)t * N + j0 + lane] = my_ell;
-        coef[(size_t)t * N + j0 + lane] = my_coef;
-    }
-}
-
-// ----------------------------------------------------------------- gather --
-// Each workgroup owns one 4 KiB segment of every column and one chunk of the
-// draws of one batch of one vector; each thread owns 16 bytes of the segment
-// (4 FP32, 8 BF16 or 16 FP8 elements) and keeps FP32 accumulators in
-// registers.  UNROLL independent 16-byte loads are in flight per thread.
-// When a column is shorter than 4 KiB, the workgroup splits into `groups`
-// groups of `tpc` threads that take interleaved draws and are summed in LDS
-// at the end.  The FP8 row scale is applied once, in k_select.
+// -------------------------------------------------- draws + gather (fused) --
+// One workgroup owns one chunk of the draws of one batch of one vector and
+// TILES x 4 KiB of every column (the whole column up to 16 KiB).
+//
+// Phase 1, draws and coefficients.  Draw j of vector t is block floor(j/4)
+// of Philox4x64-10 at counter (floor(j/4), t0 + t, 0, 0), key (seed, 0),
+// word j mod 4, and l = floor(r L / 2^64).  The coefficient c = s_l^T x is,
+// for a Kerdock vector, a signed sum of x: lane `ln` holds x[e] for
+// e = (ln + 64 p) * 32 + q (q < 32), so that bit q of sign word (ln + 64 p)
+// of basis b is Q_b(e), and with w = (w_hi, w_lo) the Walsh sign of e is
+// parity((ln + 64 p) & w_hi) ^ parity(q & w_lo).  The sum is exact: x is
+// converted once to fixed point x_int = x 2^E with sum |x_int| <= 2^30, and
+// -x_int = (x_int ^ -1) + 1, so sum_q s_q x_q = sum_q (x_q ^ m_q) + popcount
+// of the negative signs, with m_q in {0, -1}; the only roundings are that of
+// x to the 2^-E grid and of the final integer to FP32.  An identity vector
+// gives sqrt(d) x[w] (zero for w >= n).  The (l, c) pairs go to LDS.
+//
+// Phase 2, the hot loop: stream the columns T[l] and accumulate c T[l] in
+// FP32 registers; each thread owns TILES x 16 bytes (4 FP32, 8 BF16 or 16
+// FP8 entries per 16 bytes), UNROLL draws (UNROLL x TILES loads) in flight.
+// Columns shorter than 4 KiB split the workgroup into groups of `tpc`
+// threads that take interleaved draws and are summed in LDS.  The FP8 row
+// scale is applied once, in k_select.
 template <int DT> struct Elems { static constexpr int N = DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 8 : 16; };
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <int DT>
 __device__ __forceinline__ void accumulate(float *acc, const u32x4 raw, float c) {
@@ -159,82 +88,220 @@ __device__ __forceinline__ void accumulate(float *acc, const u32x4 raw, float c)
             acc[2 * e + 1] = fmaf(c, __uint_as_float(w[e] & 0xFFFF0000u), acc[2 * e + 1]);
         }
     } else {
+        // gfx950 converts OCP E4M3 in hardware, two entries per instruction
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[4 * e + s] = fmaf(c, e4m3_to_f32((w[e] >> (8 * s)) & 0xFFu), acc[4 * e + s]);
+        for (int e = 0; e < 4; ++e) {
+            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], false);
+            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], true);
+            acc[4 * e + 0] = fmaf(c, lo[0], acc[4 * e + 0]);
+            acc[4 * e + 1] = fmaf(c, lo[1], acc[4 * e + 1]);
+            acc[4 * e + 2] = fmaf(c, hi[0], acc[4 * e + 2]);
+            acc[4 * e + 3] = fmaf(c, hi[1], acc[4 * e + 3]);
+        }
     }
 }
 
-constexpr int GATHER_THREADS = 256;
-constexpr int SEG_BYTES = GATHER_THREADS * 16;
+__device__ __forceinline__ int wave_sum_i32(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
 
-template <int DT, int UNROLL, bool GROUPED>
-__global__ __launch_bounds__(GATHER_THREADS) void k_gather(
-    const unsigned char *__restrict__ table, int col_bytes, const uint32_t *__restrict__ samples,
-    const float *__restrict__ coef, int N, int J, int chunk, int chunks_per_batch, int groups,
-    int tpc, int pitch, float *__restrict__ partial) {
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+constexpr int GATHER_THREADS = 256;
+constexpr int TILE_BYTES = GATHER_THREADS * 16;
+constexpr int MAX_CHUNK = 1024;
+
+template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
+__global__ __launch_bounds__(GATHER_THREADS) void k_draw_gather(
+    const unsigned char *__restrict__ table, int col_bytes, const float *__restrict__ X, int n,
+    int k, int64_t L, const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0, int N, int J,
+    int chunk, int chunks_per_batch, int groups, int tpc, int pitch, float *__restrict__ partial,
+    uint32_t *__restrict__ dbg_samples, float *__restrict__ dbg_coef) {
     constexpr int E = Elems<DT>::N;
+    __shared__ uint32_t s_ell[MAX_CHUNK];
+    __shared__ float s_coef[MAX_CHUNK];
+
     const int t = blockIdx.z;
     const int seg = blockIdx.y;
     const int cid = blockIdx.x;
     const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
     const int jbeg = kb * J + cj * chunk;
-    const int jend = min(jbeg + chunk, (kb + 1) * J);
+    const int cnt = min(chunk, (kb + 1) * J - jbeg);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // ---------------------------------------------------------- phase 1
+    {
+        const int d = 1 << k;
+        const int words = d >= 32 ? d / 32 : 1;
+        const float *x = X + (size_t)t * n;
+        float xf[P][32];
+        float asum = 0.f;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int e = (lane + 64 * p) * 32 + q;
+                xf[p][q] = e < n ? x[e] : 0.f;
+                asum += fabsf(xf[p][q]);
+            }
+        asum = wave_sum_f32(asum);
+        // scale 2^E2 with asum 2^E2 <= 2^30: asum < 2^(ea + 1), E2 = 29 - ea
+        const bool finite = asum < INFINITY;          // false for inf and NaN
+        int E2 = 0;
+        if (finite && asum > 0.f) E2 = 29 - ((int)((__float_as_uint(asum) >> 23) & 0xFF) - 127);
+        E2 = max(-120, min(E2, 120));
+        const float up = ldexpf(1.0f, E2), down = ldexpf(1.0f, -E2);
+        int xi[P][32];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
+        const float sqrt_d = sqrtf((float)d);
+
+        for (int r0 = wave * 64; r0 < cnt; r0 += 4 * 64) {
+            const int jn = min(64, cnt - r0);
+            uint32_t my_l = 0;
+            if (lane < jn) {
+                const int j = jbeg + r0 + lane;
+                uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + t), 0, 0};
+                philox4x64_10(c4, seed, 0);
+                const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
+                my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
+            }
+            float my_c = 0.f;
+            for (int jj0 = 0; jj0 < jn; jj0 += 4) {
+                uint32_t lq[4], sw[4][P];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    lq[u] = __builtin_amdgcn_readlane(my_l, min(jj0 + u, jn - 1));
+                    const uint32_t b = lq[u] >> k;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const int word = lane + 64 * p;
+                        sw[u][p] = ((int)b < d / 2 && word < words) ? signs[(size_t)b * words + word] : 0u;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (jj0 + u >= jn) break;
+                    const uint32_t b = lq[u] >> k, w = lq[u] & (uint32_t)(d - 1);
+                    float c;
+                    if ((int)b == d / 2) {
+                        c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
+                    } else {
+                        const uint32_t wlo = walsh32(w & 31u);
+                        int acc = 0;
+#pragma unroll
+                        for (int p = 0; p < P; ++p) {
+                            const uint32_t word = (uint32_t)(lane + 64 * p);
+                            if ((int)word < words) {
+                                const uint32_t par = __popc(word & (w >> 5)) & 1u;
+                                const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
+#pragma unroll
+                                for (int q = 0; q < 32; ++q)
+                                    acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
+                                acc += __popc(mask);
+                            }
+                        }
+                        acc = wave_sum_i32(acc);
+                        c = finite ? (float)acc * down : __builtin_nanf("");
+                    }
+                    if (lane == jj0 + u) my_c = c;
+                }
+            }
+            if (lane < jn) {
+                s_ell[r0 + lane] = my_l;
+                s_coef[r0 + lane] = my_c;
+                if (dbg_samples && seg == 0) {
+                    dbg_samples[(size_t)t * N + jbeg + r0 + lane] = my_l;
+                    dbg_coef[(size_t)t * N + jbeg + r0 + lane] = my_c;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------------- phase 2
     const int g = GROUPED ? (int)threadIdx.x / tpc : 0;
     const int r = GROUPED ? (int)threadIdx.x % tpc : (int)threadIdx.x;
     const int gstride = GROUPED ? groups : 1;
-    const size_t byte_off = (size_t)seg * SEG_BYTES + (size_t)r * 16;
-    const bool active = (g < gstride) && byte_off < (size_t)col_bytes;
-
-    float acc[E];
+    const size_t seg_off = (size_t)seg * TILES * TILE_BYTES;
+    bool tile_on[TILES];
+    bool active = false;
 #pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = 0.f;
+    for (int ti = 0; ti < TILES; ++ti) {
+        tile_on[ti] = (g < gstride) && seg_off + (size_t)ti * TILE_BYTES + (size_t)r * 16 < (size_t)col_bytes;
+        active |= tile_on[ti];
+    }
 
-    const uint32_t *sp = samples + (size_t)t * N;
-    const float *cp = coef + (size_t)t * N;
+    float acc[TILES][E];
+#pragma unroll
+    for (int ti = 0; ti < TILES; ++ti)
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[ti][e] = 0.f;
+
     if (active) {
-        const unsigned char *base = table + byte_off;
-        int j = jbeg + g;
-        for (; j + (UNROLL - 1) * gstride < jend; j += UNROLL * gstride) {
-            u32x4 raw[UNROLL];
+        const unsigned char *base = table + seg_off + (size_t)r * 16;
+        int j = g;
+        for (; j + (UNROLL - 1) * gstride < cnt; j += UNROLL * gstride) {
+            u32x4 raw[UNROLL][TILES];
             float cc[UNROLL];
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t l = sp[j + u * gstride];
-                cc[u] = cp[j + u * gstride];
-                raw[u] = __builtin_nontemporal_load(
-                    reinterpret_cast<const u32x4 *>(base + (size_t)l * (size_t)col_bytes));
+                const uint32_t l = s_ell[j + u * gstride];
+                cc[u] = s_coef[j + u * gstride];
+                const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
+#pragma unroll
+                for (int ti = 0; ti < TILES; ++ti)
+                    raw[u][ti] = tile_on[ti] ? __builtin_nontemporal_load(
+                                                   reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES))
+                                             : u32x4{0u, 0u, 0u, 0u};
             }
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) accumulate<DT>(acc, raw[u], cc[u]);
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int ti = 0; ti < TILES; ++ti) accumulate<DT>(acc[ti], raw[u][ti], cc[u]);
         }
-        for (; j < jend; j += gstride) {
-            const uint32_t l = sp[j];
-            const u32x4 raw = __builtin_nontemporal_load(
-                reinterpret_cast<const u32x4 *>(base + (size_t)l * (size_t)col_bytes));
-            accumulate<DT>(acc, raw, cp[j]);
+        for (; j < cnt; j += gstride) {
+            const uint32_t l = s_ell[j];
+            const float c = s_coef[j];
+            const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
+#pragma unroll
+            for (int ti = 0; ti < TILES; ++ti)
+                if (tile_on[ti])
+                    accumulate<DT>(acc[ti], __builtin_nontemporal_load(
+                                                reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES)), c);
         }
     }
 
     if constexpr (GROUPED) {
         __shared__ float red[GATHER_THREADS * E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) red[e * GATHER_THREADS + threadIdx.x] = acc[e];
+        for (int e = 0; e < E; ++e) red[e * GATHER_THREADS + threadIdx.x] = acc[0][e];
         __syncthreads();
         if (g != 0 || !active) return;
         for (int gg = 1; gg < groups; ++gg)
 #pragma unroll
-            for (int e = 0; e < E; ++e) acc[e] += red[e * GATHER_THREADS + gg * tpc + r];
+            for (int e = 0; e < E; ++e) acc[0][e] += red[e * GATHER_THREADS + gg * tpc + r];
     } else {
         if (!active) return;
     }
     const size_t nchunks = (size_t)gridDim.x;
-    float *dst = partial + ((size_t)t * nchunks + cid) * pitch + byte_off / (16 / E);
+    float *dst = partial + ((size_t)t * nchunks + cid) * pitch;
 #pragma unroll
-    for (int e = 0; e < E; e += 4)
-        *reinterpret_cast<float4 *>(dst + e) = make_float4(acc[e], acc[e + 1], acc[e + 2], acc[e + 3]);
+    for (int ti = 0; ti < TILES; ++ti) {
+        if (!tile_on[ti]) continue;
+        float *dti = dst + (seg_off + (size_t)ti * TILE_BYTES + (size_t)r * 16) / (16 / E);
+#pragma unroll
+        for (int e = 0; e < E; e += 4)
+            *reinterpret_cast<float4 *>(dti + e) = make_float4(acc[ti][e], acc[ti][e + 1], acc[ti][e + 2], acc[ti][e + 3]);
+    }
 }
 
 // ---------------------------------------------------------------- select --
@@ -480,33 +547,25 @@ __global__ __launch_bounds__(256) void k_survivors(
 
 // -------------------------------------------------------------- launchers --
 
-int launch_sample_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs,
-                       uint64_t seed, int64_t t0, int N, uint32_t *samples, float *coef,
-                       hipStream_t s) {
-    const int waves = (N + 63) / 64;
-    dim3 grid((waves + 3) / 4, batch);
-    if (n <= 2048)
-        hipLaunchKernelGGL(k_sample_coef<1>, grid, dim3(256), 0, s, X, n, k, L, signs, seed, t0, N, samples, coef);
-    else
-        hipLaunchKernelGGL(k_sample_coef<2>, grid, dim3(256), 0, s, X, n, k, L, signs, seed, t0, N, samples, coef);
-    KD_LAUNCH("k_sample_coef");
-    return KERDOCK_OK;
-}
-
 // geometry of the gather for one handle
 struct GatherShape {
-    int col_bytes, segs, groups, tpc, grouped;
+    int col_bytes, tiles, segs, groups, tpc, grouped;
 };
 
-GatherShape gather_shape(kerdock_dtype dt, int pitch) {
+static GatherShape gather_shape(kerdock_dtype dt, int pitch) {
     GatherShape g;
     g.col_bytes = pitch * (int)dtype_bytes(dt);
-    g.segs = (g.col_bytes + SEG_BYTES - 1) / SEG_BYTES;
-    if (g.col_bytes >= SEG_BYTES) {
+    if (g.col_bytes >= TILE_BYTES) {
+        const int need = (g.col_bytes + TILE_BYTES - 1) / TILE_BYTES;
+        g.tiles = need >= 4 ? 4 : need;                 // 1, 2, 3 -> 4 ... see below
+        if (g.tiles == 3) g.tiles = 4;
+        g.segs = (g.col_bytes + g.tiles * TILE_BYTES - 1) / (g.tiles * TILE_BYTES);
         g.groups = 1;
         g.tpc = GATHER_THREADS;
         g.grouped = 0;
     } else {
+        g.tiles = 1;
+        g.segs = 1;
         g.tpc = g.col_bytes / 16;
         g.groups = GATHER_THREADS / g.tpc;
         g.grouped = 1;
@@ -514,38 +573,63 @@ GatherShape gather_shape(kerdock_dtype dt, int pitch) {
     return g;
 }
 
-template <int DT, int U>
-static void gather_dt(dim3 grid, const GatherShape &g, const void *table, const uint32_t *samples,
-                      const float *coef, int N, int J, int chunk, int cpb, int pitch, float *partial,
-                      hipStream_t s) {
+int gather_chunk_max() { return MAX_CHUNK; }
+
+template <int DT, int TILES, int U, bool GR>
+static void launch_dg(dim3 grid, const GatherShape &g, const void *table, const float *X, int n, int k,
+                      int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int N, int J,
+                      int chunk, int cpb, int pitch, float *partial, uint32_t *dbg_samples,
+                      float *dbg_coef, hipStream_t s) {
     const unsigned char *tb = reinterpret_cast<const unsigned char *>(table);
-    if (g.grouped)
-        hipLaunchKernelGGL((k_gather<DT, U, true>), grid, dim3(GATHER_THREADS), 0, s, tb, g.col_bytes,
-                           samples, coef, N, J, chunk, cpb, g.groups, g.tpc, pitch, partial);
+    if (n <= 2048)
+        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 1>), grid, dim3(GATHER_THREADS), 0, s, tb,
+                           g.col_bytes, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, g.groups, g.tpc,
+                           pitch, partial, dbg_samples, dbg_coef);
     else
-        hipLaunchKernelGGL((k_gather<DT, U, false>), grid, dim3(GATHER_THREADS), 0, s, tb, g.col_bytes,
-                           samples, coef, N, J, chunk, cpb, g.groups, g.tpc, pitch, partial);
+        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 2>), grid, dim3(GATHER_THREADS), 0, s, tb,
+                           g.col_bytes, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, g.groups, g.tpc,
+                           pitch, partial, dbg_samples, dbg_coef);
 }
 
-int launch_gather(kerdock_dtype dt, const void *table, int pitch, const uint32_t *samples,
-                  const float *coef, int batch, int N, int J, int K, int chunk, int unroll,
-                  float *partial, hipStream_t s) {
+template <int DT>
+static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const void *table, const float *X,
+                      int n, int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int N,
+                      int J, int chunk, int cpb, int pitch, float *partial, uint32_t *dbg_samples,
+                      float *dbg_coef, hipStream_t s) {
+#define KD_DG(T, U, GR) launch_dg<DT, T, U, GR>(grid, g, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s)
+    if (g.grouped) {
+        if (unroll <= 4) KD_DG(1, 4, true); else KD_DG(1, 8, true);
+    } else if (g.tiles == 1) {
+        if (unroll <= 4) KD_DG(1, 4, false); else if (unroll >= 16) KD_DG(1, 16, false); else KD_DG(1, 8, false);
+    } else if (g.tiles == 2) {
+        if (unroll <= 4) KD_DG(2, 4, false); else KD_DG(2, 8, false);
+    } else {
+        if (unroll <= 2) KD_DG(4, 2, false); else KD_DG(4, 4, false);
+    }
+#undef KD_DG
+}
+
+int launch_draw_gather(kerdock_dtype dt, const void *table, int pitch, const float *X, int batch, int n,
+                       int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int J, int K,
+                       int chunk, int unroll, float *partial, uint32_t *dbg_samples, float *dbg_coef,
+                       hipStream_t s) {
+    if (chunk < 1 || chunk > MAX_CHUNK) return fail(KERDOCK_ERR_INVALID_ARG, "gather chunk out of range");
     const GatherShape g = gather_shape(dt, pitch);
     const int cpb = (J + chunk - 1) / chunk;
+    const int N = J * K;
     dim3 grid(K * cpb, g.segs, batch);
-#define KD_GATHER_U(DT)                                                                       \
-    switch (unroll) {                                                                         \
-    case 4: gather_dt<DT, 4>(grid, g, table, samples, coef, N, J, chunk, cpb, pitch, partial, s); break; \
-    case 16: gather_dt<DT, 16>(grid, g, table, samples, coef, N, J, chunk, cpb, pitch, partial, s); break; \
-    default: gather_dt<DT, 8>(grid, g, table, samples, coef, N, J, chunk, cpb, pitch, partial, s); break; \
-    }
     switch (dt) {
-    case KERDOCK_F32: KD_GATHER_U(KERDOCK_F32) break;
-    case KERDOCK_BF16: KD_GATHER_U(KERDOCK_BF16) break;
-    case KERDOCK_FP8E4M3: KD_GATHER_U(KERDOCK_FP8E4M3) break;
+    case KERDOCK_F32:
+        launch_dt<KERDOCK_F32>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
+        break;
+    case KERDOCK_BF16:
+        launch_dt<KERDOCK_BF16>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
+        break;
+    case KERDOCK_FP8E4M3:
+        launch_dt<KERDOCK_FP8E4M3>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
+        break;
     }
-#undef KD_GATHER_U
-    KD_LAUNCH("k_gather");
+    KD_LAUNCH("k_draw_gather");
     return KERDOCK_OK;
 }
 

@@ -22,10 +22,13 @@ def table_tol(A64, k):
 
 
 def coef_tol(x64, n):
-    """c = s^T x on the GPU: 32 (64 for n > 2048) sequential adds per lane and
-    a 6-level cross-lane tree."""
+    """c = s^T x on the GPU: an exact integer signed sum of x rounded to a
+    fixed-point grid of spacing <= |x|_1 2^-29 (n roundings of half a step),
+    then one FP32 rounding; also covers a plain FP32 summation (32 or 64
+    sequential adds per lane and a 6-level cross-lane tree)."""
     P = 1 if n <= 2048 else 2
-    return (32 * P + 6 + 2) * U32 * np.abs(x64).sum()
+    a = np.abs(x64).sum()
+    return max((32 * P + 8) * U32, n * 2.0 ** -30 + 2 * U32) * a
 
 
 def quant_interval_check(orc, gpu, lo, hi, mode, scale=None):
