@@ -145,6 +145,80 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
  */
 int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max);
 
+/*
+ * kerdock_autotune -- pick the gather shape for this handle: draws per
+ * workgroup (256, 512, 1024) and draws in flight per thread, by timing the
+ * draws + gather kernel on X (device, batch x n) with N = J K draws, three
+ * runs each (the first one discarded).  The choice is kept in the handle for
+ * later calls and, when the environment variable KERDOCK_TUNE_CACHE names a
+ * file, appended to it and read back by later kerdock_prepare calls of the
+ * same shape.  Outputs (host, optional): best_chunk, best_unroll, best_ms.
+ * Synchronous.  Errors: NOT_PREPARED, INVALID_ARG, OOM, HIP.
+ */
+int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, void *stream,
+                     int *best_chunk, int *best_unroll, float *best_ms);
+
+/* ----------------------------------------------------------------------- */
+/* Batched form: several prepared matrices in one persistent launch.        */
+/* ----------------------------------------------------------------------- */
+
+#define KERDOCK_MAX_MULTI 8
+
+typedef struct kerdock_multi_s *kerdock_multi;
+
+/*
+ * kerdock_multi_create -- a plan that runs the streaming step of Algorithm 1
+ * for nh (1..8) prepared matrices at once.  Per handle q: X[q] device rows
+ * [batch[q]][n_q] (batch[q] >= 1), params[q] (J, K, seed, t0 and tau; the
+ * debug and timing fields are ignored), s_max[q] in [1, m_q] and device
+ * outputs out_idx[q], out_val[q] [batch[q]][s_max[q]], out_cnt[q]
+ * [batch[q]] with the meaning of kerdock_sparse_apply.  All handles must
+ * share one table dtype and have columns of at most 16 KiB.  The pointers are
+ * bound to the plan: every run reads the current contents of X[q] and
+ * rewrites the outputs.  The plan owns a workspace (allocated here) and
+ * must not outlive its handles.  Each handle's tuned draws-per-workgroup
+ * (kerdock_autotune) is used.  Errors: INVALID_ARG, NOT_PREPARED, OOM, HIP.
+ */
+int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X, const int *batch,
+                         const kerdock_apply_params *params, float eps, const int *s_max,
+                         int32_t *const *out_idx, float *const *out_val, int32_t *const *out_cnt,
+                         kerdock_multi *out);
+
+/*
+ * kerdock_multi_run -- enqueue one pass on `stream` (kernels only, no
+ * allocation, no memset, no synchronisation, so it can be captured in a
+ * graph): the draws + gather of every (handle, vector, chunk) work item in one
+ * persistent launch whose workgroups take items longest-column first, then
+ * selection and survivor dots for every vector, then every stream position
+ * advances by its batch, so that consecutive runs draw for consecutive
+ * stream positions (the results for handle q equal those of
+ * kerdock_sparse_apply at the same stream position).
+ */
+int kerdock_multi_run(kerdock_multi plan, void *stream);
+
+/* kerdock_multi_set_position -- set the stream positions (host t0[nh]) of the
+ * next run.  Synchronises the device. */
+int kerdock_multi_set_position(kerdock_multi plan, const int64_t *t0);
+
+/* kerdock_multi_graph_launch -- on the first call capture one run into a HIP
+ * graph owned by the plan; launch that graph on `stream`. */
+int kerdock_multi_graph_launch(kerdock_multi plan, void *stream);
+
+/* kerdock_multi_autotune -- time the persistent gather with each available
+ * unroll depth (two runs each) and keep the fastest (host best_unroll,
+ * optional).  Drops a previously captured graph.  Synchronous. */
+int kerdock_multi_autotune(kerdock_multi plan, void *stream, int *best_unroll);
+
+/* kerdock_multi_destroy -- free the plan (after synchronising the device). */
+int kerdock_multi_destroy(kerdock_multi plan);
+
+/* kerdock_sparse_apply_multi -- create a plan, run it once, synchronise
+ * `stream`, destroy the plan. */
+int kerdock_sparse_apply_multi(const kerdock_handle *hs, int nh, const float *const *X, const int *batch,
+                               const kerdock_apply_params *params, float eps, const int *s_max,
+                               int32_t *const *out_idx, float *const *out_val, int32_t *const *out_cnt,
+                               void *stream);
+
 /* kerdock_query -- geometry of a handle; `info` is host memory. */
 int kerdock_query(kerdock_handle h, kerdock_info *info);
 

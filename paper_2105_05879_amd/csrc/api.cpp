@@ -5,10 +5,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <stdio.h>
+
+#include <algorithm>
 #include <string>
 #include <vector>
 
-#include "common.hpp"
+#include "apply_device.hpp"
 
 namespace kd {
 
@@ -23,17 +26,10 @@ int launch_table_build(kerdock_dtype dt, int k, const float *A, int m, int n, in
 int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, int64_t L,
                         const float *scales, const uint32_t *ells, int count, float *out,
                         hipStream_t s);
-int launch_draw_gather(kerdock_dtype dt, const void *table, int pitch, const float *X, int batch, int n,
-                       int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int J, int K,
-                       int chunk, int unroll, float *partial, uint32_t *dbg_samples, float *dbg_coef,
-                       hipStream_t s);
+int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int unroll, hipStream_t s);
 int gather_chunk_max();
-int launch_select(const float *partial, int batch, int m, int pitch, int K, int cpb, int J,
-                  const float *scales, int s_max, float tau, float *mu_out, int32_t *surv,
-                  int32_t *nsurv, hipStream_t s);
-int launch_survivors(const float *A, int n, const float *X, int batch, const int32_t *surv,
-                     const int32_t *nsurv, int s_max, float eps, int32_t *out_idx, float *out_val,
-                     int32_t *out_cnt, float *dbg_values, hipStream_t s);
+int launch_select(const SelArgs &a, int batch, hipStream_t s);
+int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
 
 static thread_local std::string g_error;
 
@@ -57,14 +53,16 @@ static int env_int(const char *name, int dflt) {
     return atoi(v);
 }
 
-static int gather_chunk(int J) {
-    int c = env_int("KERDOCK_CHUNK", 512);
+static int gather_chunk(const kerdock_handle_s *h, int J) {
+    int c = env_int("KERDOCK_CHUNK", h->tune_chunk > 0 ? h->tune_chunk : 512);
     if (c < 16) c = 16;
     if (c > gather_chunk_max()) c = gather_chunk_max();
     return c < J ? c : J;
 }
 
-static int gather_unroll() { return env_int("KERDOCK_UNROLL", 8); }
+static int gather_unroll(const kerdock_handle_s *h) {
+    return env_int("KERDOCK_UNROLL", h->tune_unroll > 0 ? h->tune_unroll : 8);
+}
 
 // workspace layout of the streaming step
 struct Workspace {
@@ -75,7 +73,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max) {
     const size_t N = (size_t)J * K;
-    const int chunk = gather_chunk(J);
+    const int chunk = gather_chunk(h, J);
     const size_t cpb = (J + chunk - 1) / chunk;
     Workspace w;
     size_t off = 0;
@@ -106,15 +104,40 @@ static int ensure_workspace(kerdock_handle_s *h, size_t bytes) {
 
 static void free_handle(kerdock_handle_s *h) {
     if (!h) return;
-    hipFree(h->table);
-    hipFree(h->scales);
-    hipFree(h->A);
-    hipFree(h->signs);
-    hipFree(h->masks);
-    hipFree(h->ws);
+    (void)hipFree(h->table);
+    (void)hipFree(h->scales);
+    (void)hipFree(h->A);
+    (void)hipFree(h->signs);
+    (void)hipFree(h->masks);
+    (void)hipFree(h->ws);
     for (int q = 0; q < 5; ++q)
-        if (h->ev[q]) hipEventDestroy(h->ev[q]);
+        if (h->ev[q]) (void)hipEventDestroy(h->ev[q]);
     delete h;
+}
+
+// Tuning cache: one line "m n dtype K chunk unroll" per tuned shape, in the
+// file named by KERDOCK_TUNE_CACHE (read at prepare, appended by autotune).
+static void cache_lookup(kerdock_handle_s *h) {
+    const char *path = getenv("KERDOCK_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    int m, n, dt, K, c, u;
+    while (fscanf(f, "%d %d %d %d %d %d", &m, &n, &dt, &K, &c, &u) == 6)
+        if (m == h->m && n == h->n && dt == (int)h->dtype) {
+            h->tune_chunk = c;
+            h->tune_unroll = u;
+        }
+    fclose(f);
+}
+
+static void cache_store(const kerdock_handle_s *h, int K) {
+    const char *path = getenv("KERDOCK_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%d %d %d %d %d %d\n", h->m, h->n, (int)h->dtype, K, h->tune_chunk, h->tune_unroll);
+    fclose(f);
 }
 
 }  // namespace kd
@@ -192,6 +215,7 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
         free_handle(h);
         return rc;
     }
+    cache_lookup(h);
     *out = h;
     return KERDOCK_OK;
 }
@@ -228,7 +252,7 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     float *partial = reinterpret_cast<float *>(ws + lay.partial);
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
-    const int chunk = gather_chunk(J);
+    const int chunk = gather_chunk(h, J);
     const int cpb = (J + chunk - 1) / chunk;
     if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
         return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
@@ -239,16 +263,37 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     if (timed && !h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
     if (timed) KD_HIP(hipEventRecord(h->ev[1], s));
-    rc = launch_draw_gather(h->dtype, h->table, h->pitch, X, batch, h->n, h->k, h->L, h->signs, p->seed,
-                            p->t0, J, K, chunk, gather_unroll(), partial, p->dbg_samples, p->dbg_coef, s);
+    DGArgs dg{};
+    dg.table = reinterpret_cast<const unsigned char *>(h->table);
+    dg.col_bytes = h->pitch * (int)dtype_bytes(h->dtype);
+    dg.X = X;
+    dg.n = h->n;
+    dg.k = h->k;
+    dg.L = h->L;
+    dg.signs = h->signs;
+    dg.seed = p->seed;
+    dg.t0_dev = nullptr;
+    dg.t0 = p->t0;
+    dg.N = N;
+    dg.J = J;
+    dg.chunk = chunk;
+    dg.chunks_per_batch = cpb;
+    {
+        const GatherShape gs = gather_shape(h->dtype, h->pitch);
+        dg.groups = gs.groups;
+        dg.tpc = gs.tpc;
+    }
+    dg.pitch = h->pitch;
+    dg.partial = partial;
+    dg.dbg_samples = p->dbg_samples;
+    dg.dbg_coef = p->dbg_coef;
+    rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
-    if (rc == KERDOCK_OK)
-        rc = launch_select(partial, batch, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau,
-                           p->dbg_mu, surv, nsurv, s);
+    SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv};
+    if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
-    if (rc == KERDOCK_OK)
-        rc = launch_survivors(h->A, h->n, X, batch, surv, nsurv, s_max, eps, out_idx, out_val,
-                              out_cnt, p->dbg_values, s);
+    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values};
+    if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;
     if (timed) {
@@ -258,6 +303,78 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
     }
     if (p->dbg_survivors)
         KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
+    return KERDOCK_OK;
+}
+
+int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, void *stream,
+                     int *best_chunk, int *best_unroll, float *best_ms) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!X || batch < 1 || J < 1 || K < 1 || K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "autotune: bad arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const GatherShape gs = gather_shape(h->dtype, h->pitch);
+    std::vector<int> unrolls;
+    if (gs.grouped) unrolls = {4, 8};
+    else if (gs.tiles == 1) unrolls = {4, 8, 16};
+    else if (gs.tiles == 2) unrolls = {4, 8};
+    else unrolls = {2, 4};
+    const int chunks[] = {256, 512, 1024};
+    size_t need = 0;
+    for (int c : chunks) {
+        const size_t cc = std::min(c, J);
+        need = std::max(need, (size_t)batch * K * ((J + cc - 1) / cc) * h->pitch * 4);
+    }
+    int rc = ensure_workspace(h, need);
+    if (rc != KERDOCK_OK) return rc;
+    if (!h->ev[0])
+        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
+    float best = 1e30f;
+    int bc = 512, bu = 8;
+    for (int c : chunks) {
+        const int chunk = std::min(c, J);
+        if (c > J && c != chunks[0]) continue;
+        for (int u : unrolls) {
+            DGArgs dg{};
+            dg.table = reinterpret_cast<const unsigned char *>(h->table);
+            dg.col_bytes = gs.col_bytes;
+            dg.X = X;
+            dg.n = h->n;
+            dg.k = h->k;
+            dg.L = h->L;
+            dg.signs = h->signs;
+            dg.seed = 12345;
+            dg.t0 = 0;
+            dg.N = J * K;
+            dg.J = J;
+            dg.chunk = chunk;
+            dg.chunks_per_batch = (J + chunk - 1) / chunk;
+            dg.groups = gs.groups;
+            dg.tpc = gs.tpc;
+            dg.pitch = h->pitch;
+            dg.partial = reinterpret_cast<float *>(h->ws);
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                KD_HIP(hipEventRecord(h->ev[0], s));
+                rc = launch_draw_gather(h->dtype, dg, batch, K, u, s);
+                if (rc != KERDOCK_OK) return rc;
+                KD_HIP(hipEventRecord(h->ev[1], s));
+                KD_HIP(hipEventSynchronize(h->ev[1]));
+                float ms = 0.f;
+                KD_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+                if (rep > 0) tmin = std::min(tmin, ms);     // first run warms up
+            }
+            if (tmin < best) {
+                best = tmin;
+                bc = chunk;
+                bu = u;
+            }
+        }
+    }
+    h->tune_chunk = bc;
+    h->tune_unroll = bu;
+    cache_store(h, K);
+    if (best_chunk) *best_chunk = bc;
+    if (best_unroll) *best_unroll = bu;
+    if (best_ms) *best_ms = best;
     return KERDOCK_OK;
 }
 
@@ -301,8 +418,8 @@ int kerdock_row_scales(kerdock_handle h, float *out, void *stream) {
 
 int kerdock_destroy(kerdock_handle h) {
     if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
-    hipSetDevice(h->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
     free_handle(h);
     return KERDOCK_OK;
 }

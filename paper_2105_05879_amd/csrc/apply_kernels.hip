@@ -1,564 +1,41 @@
-// Streaming-step kernels (Algorithm 1 streaming step, Theorem 5) for gfx950.
-//
-//   k_sample_coef  draw l_j uniformly from [L] (Philox4x64-10) and compute the
-//                  coefficient c_j = s_{l_j}^T x: a signed Walsh sum of x for
-//                  Kerdock vectors, sqrt(d) x[w] for identity vectors;
-//   k_gather       the hot loop: stream the drawn table columns from HBM and
-//                  accumulate c_j T[l_j] per chunk of draws of one batch;
-//   k_select       batch means, entrywise median over the K batches, and the
-//                  s_max rows of largest |mu| (ties: smaller index) by an
-//                  LDS radix select, compacted in ascending row order;
-//   k_survivors    exact a_i.x on the selected rows (compensated FP32 dot
-//                  product, Ogita-Rump-Oishi Dot2) and the eps threshold.
-#include "common.hpp"
+// Single-handle kernels of the streaming step: thin wrappers around the
+// device code in apply_device.hpp, one launch per stage.
+#include "apply_device.hpp"
 
 namespace kd {
 
-// ----------------------------------------------------------------- Philox --
-// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 64 x 64 -> 128-bit products with a Weyl key schedule.
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += W0;
-            k1 += W1;
-        }
-        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
-        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
-// bit q of the result is parity(q & v), q < 32 (Walsh functions on 5 bits)
-__device__ __forceinline__ uint32_t walsh32(uint32_t v) {
-    uint32_t w = 0;
-    if (v & 1u) w ^= 0xAAAAAAAAu;
-    if (v & 2u) w ^= 0xCCCCCCCCu;
-    if (v & 4u) w ^= 0xF0F0F0F0u;
-    if (v & 8u) w ^= 0xFF00FF00u;
-    if (v & 16u) w ^= 0xFFFF0000u;
-    return w;
-}
-
-// -------------------------------------------------- draws + gather (fused) --
-// One workgroup owns one chunk of the draws of one batch of one vector and
-// TILES x 4 KiB of every column (the whole column up to 16 KiB).
-//
-// Phase 1, draws and coefficients.  Draw j of vector t is block floor(j/4)
-// of Philox4x64-10 at counter (floor(j/4), t0 + t, 0, 0), key (seed, 0),
-// word j mod 4, and l = floor(r L / 2^64).  The coefficient c = s_l^T x is,
-// for a Kerdock vector, a signed sum of x: lane `ln` holds x[e] for
-// e = (ln + 64 p) * 32 + q (q < 32), so that bit q of sign word (ln + 64 p)
-// of basis b is Q_b(e), and with w = (w_hi, w_lo) the Walsh sign of e is
-// parity((ln + 64 p) & w_hi) ^ parity(q & w_lo).  The sum is exact: x is
-// converted once to fixed point x_int = x 2^E with sum |x_int| <= 2^30, and
-// -x_int = (x_int ^ -1) + 1, so sum_q s_q x_q = sum_q (x_q ^ m_q) + popcount
-// of the negative signs, with m_q in {0, -1}; the only roundings are that of
-// x to the 2^-E grid and of the final integer to FP32.  An identity vector
-// gives sqrt(d) x[w] (zero for w >= n).  The (l, c) pairs go to LDS.
-//
-// Phase 2, the hot loop: stream the columns T[l] and accumulate c T[l] in
-// FP32 registers; each thread owns TILES x 16 bytes (4 FP32, 8 BF16 or 16
-// FP8 entries per 16 bytes), UNROLL draws (UNROLL x TILES loads) in flight.
-// Columns shorter than 4 KiB split the workgroup into groups of `tpc`
-// threads that take interleaved draws and are summed in LDS.  The FP8 row
-// scale is applied once, in k_select.
-template <int DT> struct Elems { static constexpr int N = DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 8 : 16; };
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-
-template <int DT>
-__device__ __forceinline__ void accumulate(float *acc, const u32x4 raw, float c) {
-    const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-    if constexpr (DT == KERDOCK_F32) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[e] = fmaf(c, __uint_as_float(w[e]), acc[e]);
-    } else if constexpr (DT == KERDOCK_BF16) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            acc[2 * e] = fmaf(c, __uint_as_float(w[e] << 16), acc[2 * e]);
-            acc[2 * e + 1] = fmaf(c, __uint_as_float(w[e] & 0xFFFF0000u), acc[2 * e + 1]);
-        }
-    } else {
-        // gfx950 converts OCP E4M3 in hardware, two entries per instruction
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], false);
-            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], true);
-            acc[4 * e + 0] = fmaf(c, lo[0], acc[4 * e + 0]);
-            acc[4 * e + 1] = fmaf(c, lo[1], acc[4 * e + 1]);
-            acc[4 * e + 2] = fmaf(c, hi[0], acc[4 * e + 2]);
-            acc[4 * e + 3] = fmaf(c, hi[1], acc[4 * e + 3]);
-        }
-    }
-}
-
-__device__ __forceinline__ int wave_sum_i32(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum_f32(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-constexpr int GATHER_THREADS = 256;
-constexpr int TILE_BYTES = GATHER_THREADS * 16;
-constexpr int MAX_CHUNK = 1024;
-
 template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
-__global__ __launch_bounds__(GATHER_THREADS) void k_draw_gather(
-    const unsigned char *__restrict__ table, int col_bytes, const float *__restrict__ X, int n,
-    int k, int64_t L, const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0, int N, int J,
-    int chunk, int chunks_per_batch, int groups, int tpc, int pitch, float *__restrict__ partial,
-    uint32_t *__restrict__ dbg_samples, float *__restrict__ dbg_coef) {
+__global__ __launch_bounds__(GATHER_THREADS) void k_draw_gather(DGArgs a) {
     constexpr int E = Elems<DT>::N;
     __shared__ uint32_t s_ell[MAX_CHUNK];
     __shared__ float s_coef[MAX_CHUNK];
-
-    const int t = blockIdx.z;
-    const int seg = blockIdx.y;
-    const int cid = blockIdx.x;
-    const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
-    const int jbeg = kb * J + cj * chunk;
-    const int cnt = min(chunk, (kb + 1) * J - jbeg);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // ---------------------------------------------------------- phase 1
-    {
-        const int d = 1 << k;
-        const int words = d >= 32 ? d / 32 : 1;
-        const float *x = X + (size_t)t * n;
-        float xf[P][32];
-        float asum = 0.f;
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int e = (lane + 64 * p) * 32 + q;
-                xf[p][q] = e < n ? x[e] : 0.f;
-                asum += fabsf(xf[p][q]);
-            }
-        asum = wave_sum_f32(asum);
-        // scale 2^E2 with asum 2^E2 <= 2^30: asum < 2^(ea + 1), E2 = 29 - ea
-        const bool finite = asum < INFINITY;          // false for inf and NaN
-        int E2 = 0;
-        if (finite && asum > 0.f) E2 = 29 - ((int)((__float_as_uint(asum) >> 23) & 0xFF) - 127);
-        E2 = max(-120, min(E2, 120));
-        const float up = ldexpf(1.0f, E2), down = ldexpf(1.0f, -E2);
-        int xi[P][32];
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
-        const float sqrt_d = sqrtf((float)d);
-
-        for (int r0 = wave * 64; r0 < cnt; r0 += 4 * 64) {
-            const int jn = min(64, cnt - r0);
-            uint32_t my_l = 0;
-            if (lane < jn) {
-                const int j = jbeg + r0 + lane;
-                uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + t), 0, 0};
-                philox4x64_10(c4, seed, 0);
-                const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
-                my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
-            }
-            float my_c = 0.f;
-            for (int jj0 = 0; jj0 < jn; jj0 += 4) {
-                uint32_t lq[4], sw[4][P];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    lq[u] = __builtin_amdgcn_readlane(my_l, min(jj0 + u, jn - 1));
-                    const uint32_t b = lq[u] >> k;
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const int word = lane + 64 * p;
-                        sw[u][p] = ((int)b < d / 2 && word < words) ? signs[(size_t)b * words + word] : 0u;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (jj0 + u >= jn) break;
-                    const uint32_t b = lq[u] >> k, w = lq[u] & (uint32_t)(d - 1);
-                    float c;
-                    if ((int)b == d / 2) {
-                        c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
-                    } else {
-                        const uint32_t wlo = walsh32(w & 31u);
-                        int acc = 0;
-#pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const uint32_t word = (uint32_t)(lane + 64 * p);
-                            if ((int)word < words) {
-                                const uint32_t par = __popc(word & (w >> 5)) & 1u;
-                                const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
-#pragma unroll
-                                for (int q = 0; q < 32; ++q)
-                                    acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
-                                acc += __popc(mask);
-                            }
-                        }
-                        acc = wave_sum_i32(acc);
-                        c = finite ? (float)acc * down : __builtin_nanf("");
-                    }
-                    if (lane == jj0 + u) my_c = c;
-                }
-            }
-            if (lane < jn) {
-                s_ell[r0 + lane] = my_l;
-                s_coef[r0 + lane] = my_c;
-                if (dbg_samples && seg == 0) {
-                    dbg_samples[(size_t)t * N + jbeg + r0 + lane] = my_l;
-                    dbg_coef[(size_t)t * N + jbeg + r0 + lane] = my_c;
-                }
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---------------------------------------------------------- phase 2
-    const int g = GROUPED ? (int)threadIdx.x / tpc : 0;
-    const int r = GROUPED ? (int)threadIdx.x % tpc : (int)threadIdx.x;
-    const int gstride = GROUPED ? groups : 1;
-    const size_t seg_off = (size_t)seg * TILES * TILE_BYTES;
-    bool tile_on[TILES];
-    bool active = false;
-#pragma unroll
-    for (int ti = 0; ti < TILES; ++ti) {
-        tile_on[ti] = (g < gstride) && seg_off + (size_t)ti * TILE_BYTES + (size_t)r * 16 < (size_t)col_bytes;
-        active |= tile_on[ti];
-    }
-
-    float acc[TILES][E];
-#pragma unroll
-    for (int ti = 0; ti < TILES; ++ti)
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[ti][e] = 0.f;
-
-    if (active) {
-        const unsigned char *base = table + seg_off + (size_t)r * 16;
-        int j = g;
-        for (; j + (UNROLL - 1) * gstride < cnt; j += UNROLL * gstride) {
-            u32x4 raw[UNROLL][TILES];
-            float cc[UNROLL];
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u) {
-                const uint32_t l = s_ell[j + u * gstride];
-                cc[u] = s_coef[j + u * gstride];
-                const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
-#pragma unroll
-                for (int ti = 0; ti < TILES; ++ti)
-                    raw[u][ti] = tile_on[ti] ? __builtin_nontemporal_load(
-                                                   reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES))
-                                             : u32x4{0u, 0u, 0u, 0u};
-            }
-#pragma unroll
-            for (int u = 0; u < UNROLL; ++u)
-#pragma unroll
-                for (int ti = 0; ti < TILES; ++ti) accumulate<DT>(acc[ti], raw[u][ti], cc[u]);
-        }
-        for (; j < cnt; j += gstride) {
-            const uint32_t l = s_ell[j];
-            const float c = s_coef[j];
-            const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
-#pragma unroll
-            for (int ti = 0; ti < TILES; ++ti)
-                if (tile_on[ti])
-                    accumulate<DT>(acc[ti], __builtin_nontemporal_load(
-                                                reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES)), c);
-        }
-    }
-
-    if constexpr (GROUPED) {
-        __shared__ float red[GATHER_THREADS * E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) red[e * GATHER_THREADS + threadIdx.x] = acc[0][e];
-        __syncthreads();
-        if (g != 0 || !active) return;
-        for (int gg = 1; gg < groups; ++gg)
-#pragma unroll
-            for (int e = 0; e < E; ++e) acc[0][e] += red[e * GATHER_THREADS + gg * tpc + r];
-    } else {
-        if (!active) return;
-    }
-    const size_t nchunks = (size_t)gridDim.x;
-    float *dst = partial + ((size_t)t * nchunks + cid) * pitch;
-#pragma unroll
-    for (int ti = 0; ti < TILES; ++ti) {
-        if (!tile_on[ti]) continue;
-        float *dti = dst + (seg_off + (size_t)ti * TILE_BYTES + (size_t)r * 16) / (16 / E);
-#pragma unroll
-        for (int e = 0; e < E; e += 4)
-            *reinterpret_cast<float4 *>(dti + e) = make_float4(acc[ti][e], acc[ti][e + 1], acc[ti][e + 2], acc[ti][e + 3]);
-    }
-}
-
-// ---------------------------------------------------------------- select --
-// One workgroup per vector.  Row i: ybar_k = (sum of the chunk partials of
-// batch k) / J, mu_i = median_k ybar_k (bitonic sort over KMAX >= K slots
-// padded with +inf; even K: mean of the two middle values), times the FP8
-// row scale.  Then the s_max largest |mu| are found by a radix select over
-// the FP32 bit patterns of |mu| (non-negative floats order like their bits)
-// and written in ascending row order.
-constexpr int SELECT_THREADS = 1024;
-
-__device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int incl = v;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(incl, off);
-        if (lane >= off) incl += u;
-    }
-    if (lane == 63) sh[wave] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int w = 0; w < SELECT_THREADS / 64; ++w) {
-            const int c = sh[w];
-            sh[w] = run;
-            run += c;
-        }
-        sh[SELECT_THREADS / 64] = run;
-    }
-    __syncthreads();
-    const int res = sh[wave] + incl - v;
-    *total = sh[SELECT_THREADS / 64];
-    __syncthreads();
-    return res;
+    __shared__ float red[GROUPED ? GATHER_THREADS * E : 1];
+    draw_gather<DT, TILES, UNROLL, GROUPED, P>(a, blockIdx.z, blockIdx.x, blockIdx.y, gridDim.x, s_ell,
+                                               s_coef, red);
 }
 
 template <int KMAX>
-__global__ __launch_bounds__(SELECT_THREADS) void k_select(
-    const float *__restrict__ partial, int m, int pitch, int K, int chunks_per_batch, int J,
-    const float *__restrict__ scales, int s_max, float tau, float *__restrict__ mu_out,
-    int32_t *__restrict__ surv, int32_t *__restrict__ nsurv) {
+__global__ __launch_bounds__(SELECT_THREADS) void k_select(SelArgs a) {
     extern __shared__ uint32_t key[];          // [m] bits of |mu|
     __shared__ uint32_t hist[256];
     __shared__ int scan_sh[SELECT_THREADS / 64 + 1];
-    __shared__ uint32_t sel_prefix, sel_want;
-
-    const int t = blockIdx.x;
-    const int nchunks = K * chunks_per_batch;
-    const float *pt = partial + (size_t)t * nchunks * pitch;
-    for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
-        float v[KMAX];
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            float s = INFINITY;
-            if (a < K) {
-                s = 0.f;
-                for (int c = 0; c < chunks_per_batch; ++c)
-                    s += pt[(size_t)(a * chunks_per_batch + c) * pitch + i];
-                s = s / (float)J;
-            }
-            v[a] = s;
-        }
-        // bitonic sort, ascending
-#pragma unroll
-        for (int size = 2; size <= KMAX; size <<= 1)
-#pragma unroll
-            for (int stride = size >> 1; stride > 0; stride >>= 1)
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a) {
-                    const int bb = a ^ stride;
-                    if (bb > a) {
-                        const bool up = (a & size) == 0;
-                        const float lo = fminf(v[a], v[bb]), hi = fmaxf(v[a], v[bb]);
-                        v[a] = up ? lo : hi;
-                        v[bb] = up ? hi : lo;
-                    }
-                }
-        float lo_mid = 0.f, hi_mid = 0.f;
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            if (a == (K - 1) / 2) lo_mid = v[a];
-            if (a == K / 2) hi_mid = v[a];
-        }
-        float med = (K & 1) ? hi_mid : 0.5f * (lo_mid + hi_mid);
-        med *= scales[i];
-        if (mu_out) mu_out[(size_t)t * m + i] = med;
-        key[i] = __float_as_uint(fabsf(med));
-    }
-    __syncthreads();
-
-    // radix select of the s_max-th largest key
-    uint32_t prefix = 0, fixed = 0, want = (uint32_t)s_max;
-    const bool take_all = s_max >= m;
-    if (!take_all) {
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            if (threadIdx.x < 256) hist[threadIdx.x] = 0;
-            __syncthreads();
-            for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
-                const uint32_t kk = key[i];
-                if (((kk ^ prefix) & fixed) == 0) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
-            }
-            __syncthreads();
-            if (threadIdx.x < 64) {
-                const int lane = threadIdx.x;
-                // lane owns bins 4*lane .. 4*lane+3; suffix sums from the top
-                uint32_t hb[4], tot = 0;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    hb[q] = hist[4 * lane + q];
-                    tot += hb[q];
-                }
-                // inclusive suffix scan over lanes: incl = sum of tot over lanes >= lane
-                uint32_t incl = tot;
-#pragma unroll
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t u = __shfl_down(incl, off);
-                    if (lane + off < 64) incl += u;
-                }
-                uint32_t above = incl - tot;   // keys in the bins of higher lanes
-#pragma unroll
-                for (int q = 3; q >= 0; --q) {
-                    if (above < want && want <= above + hb[q]) {
-                        sel_prefix = prefix | ((uint32_t)(4 * lane + q) << shift);
-                        sel_want = want - above;
-                    }
-                    above += hb[q];
-                }
-            }
-            __syncthreads();
-            prefix = sel_prefix;
-            want = sel_want;
-            fixed |= 255u << shift;
-            __syncthreads();
-        }
-    }
-    const uint32_t theta = prefix;
-    const uint32_t tau_bits = __float_as_uint(fmaxf(tau, 0.f));
-
-    // ascending compaction: thread owns rows [i0, i1)
-    const int per = (m + SELECT_THREADS - 1) / SELECT_THREADS;
-    const int i0 = min(m, (int)threadIdx.x * per), i1 = min(m, i0 + per);
-    int eq_local = 0;
-    if (!take_all)
-        for (int i = i0; i < i1; ++i) eq_local += key[i] == theta;
-    int eq_total;
-    int eq_rank = block_exclusive_scan(eq_local, &eq_total, scan_sh);
-    int sel_local = 0;
-    {
-        int er = eq_rank;
-        for (int i = i0; i < i1; ++i) {
-            const uint32_t kk = key[i];
-            bool sel = take_all || kk > theta || (kk == theta && (uint32_t)er < want);
-            if (!take_all && kk == theta) ++er;
-            sel = sel && kk >= tau_bits;
-            sel_local += sel;
-        }
-    }
-    int total;
-    int pos = block_exclusive_scan(sel_local, &total, scan_sh);
-    {
-        int er = eq_rank;
-        for (int i = i0; i < i1; ++i) {
-            const uint32_t kk = key[i];
-            bool sel = take_all || kk > theta || (kk == theta && (uint32_t)er < want);
-            if (!take_all && kk == theta) ++er;
-            sel = sel && kk >= tau_bits;
-            if (sel && pos < s_max) surv[(size_t)t * s_max + pos++] = i;
-        }
-    }
-    total = min(total, s_max);
-    for (int s = total + threadIdx.x; s < s_max; s += SELECT_THREADS) surv[(size_t)t * s_max + s] = -1;
-    if (threadIdx.x == 0) nsurv[t] = total;
+    __shared__ uint32_t sel_state[2];
+    select_vec<KMAX>(a, blockIdx.x, key, hist, scan_sh, sel_state);
 }
 
-// ------------------------------------------------------------- survivors --
-// Dot2 (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci.
-// Comput. 2005): error-free products and sums, so the FP32 result is as
-// accurate as if computed in twice the working precision.
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-#pragma clang fp contract(off)
-    s = a + b;
-    const float z = s - a;
-    e = (a - (s - z)) + (b - z);
-}
-
-__global__ __launch_bounds__(256) void k_survivors(
-    const float *__restrict__ A, int n, const float *__restrict__ X,
-    const int32_t *__restrict__ surv, const int32_t *__restrict__ nsurv, int s_max, float eps,
-    int32_t *__restrict__ out_idx, float *__restrict__ out_val, int32_t *__restrict__ out_cnt,
-    float *__restrict__ dbg_values) {
-#pragma clang fp contract(off)
+__global__ __launch_bounds__(SURV_THREADS) void k_survivors(SurvArgs a) {
     extern __shared__ float vals[];
-    const int t = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ns = min(nsurv[t], s_max);
-    const float *x = X + (size_t)t * n;
-    for (int s = wave; s < ns; s += 4) {
-        const int i = surv[(size_t)t * s_max + s];
-        const float *row = A + (size_t)i * n;
-        float p = 0.f, e = 0.f;
-        for (int q = lane; q < n; q += 64) {
-            const float a = row[q], b = x[q];
-            const float h = a * b;
-            const float rr = fmaf(a, b, -h);
-            float sum, err;
-            two_sum(p, h, sum, err);
-            p = sum;
-            e = e + (err + rr);
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float p2 = __shfl_xor(p, off), e2 = __shfl_xor(e, off);
-            float sum, err;
-            two_sum(p, p2, sum, err);
-            p = sum;
-            e = e + e2 + err;
-        }
-        if (lane == 0) vals[s] = p + e;
-    }
-    __syncthreads();
-    if (wave != 0) return;
-    int base = 0;
-    for (int s0 = 0; s0 < s_max; s0 += 64) {
-        const int s = s0 + lane;
-        const bool keep = s < ns && fabsf(vals[s]) >= eps;
-        const uint64_t mask = __ballot(keep);
-        const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
-        if (keep) {
-            out_idx[(size_t)t * s_max + pos] = surv[(size_t)t * s_max + s];
-            out_val[(size_t)t * s_max + pos] = vals[s];
-        }
-        base += __popcll(mask);
-    }
-    for (int s = base + lane; s < s_max; s += 64) {
-        out_idx[(size_t)t * s_max + s] = -1;
-        out_val[(size_t)t * s_max + s] = 0.f;
-    }
-    if (dbg_values)
-        for (int s = lane; s < s_max; s += 64) dbg_values[(size_t)t * s_max + s] = s < ns ? vals[s] : 0.f;
-    if (lane == 0) out_cnt[t] = base;
+    survivors_vec(a, blockIdx.x, vals);
 }
 
 // -------------------------------------------------------------- launchers --
 
-// geometry of the gather for one handle
-struct GatherShape {
-    int col_bytes, tiles, segs, groups, tpc, grouped;
-};
-
-static GatherShape gather_shape(kerdock_dtype dt, int pitch) {
+GatherShape gather_shape(kerdock_dtype dt, int pitch) {
     GatherShape g;
     g.col_bytes = pitch * (int)dtype_bytes(dt);
     if (g.col_bytes >= TILE_BYTES) {
         const int need = (g.col_bytes + TILE_BYTES - 1) / TILE_BYTES;
-        g.tiles = need >= 4 ? 4 : need;                 // 1, 2, 3 -> 4 ... see below
-        if (g.tiles == 3) g.tiles = 4;
+        g.tiles = need >= 3 ? 4 : need;
         g.segs = (g.col_bytes + g.tiles * TILE_BYTES - 1) / (g.tiles * TILE_BYTES);
         g.groups = 1;
         g.tpc = GATHER_THREADS;
@@ -576,87 +53,59 @@ static GatherShape gather_shape(kerdock_dtype dt, int pitch) {
 int gather_chunk_max() { return MAX_CHUNK; }
 
 template <int DT, int TILES, int U, bool GR>
-static void launch_dg(dim3 grid, const GatherShape &g, const void *table, const float *X, int n, int k,
-                      int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int N, int J,
-                      int chunk, int cpb, int pitch, float *partial, uint32_t *dbg_samples,
-                      float *dbg_coef, hipStream_t s) {
-    const unsigned char *tb = reinterpret_cast<const unsigned char *>(table);
-    if (n <= 2048)
-        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 1>), grid, dim3(GATHER_THREADS), 0, s, tb,
-                           g.col_bytes, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, g.groups, g.tpc,
-                           pitch, partial, dbg_samples, dbg_coef);
+static void launch_dg(dim3 grid, const DGArgs &a, hipStream_t s) {
+    if (a.n <= 2048)
+        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 1>), grid, dim3(GATHER_THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 2>), grid, dim3(GATHER_THREADS), 0, s, tb,
-                           g.col_bytes, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, g.groups, g.tpc,
-                           pitch, partial, dbg_samples, dbg_coef);
+        hipLaunchKernelGGL((k_draw_gather<DT, TILES, U, GR, 2>), grid, dim3(GATHER_THREADS), 0, s, a);
 }
 
 template <int DT>
-static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const void *table, const float *X,
-                      int n, int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int N,
-                      int J, int chunk, int cpb, int pitch, float *partial, uint32_t *dbg_samples,
-                      float *dbg_coef, hipStream_t s) {
-#define KD_DG(T, U, GR) launch_dg<DT, T, U, GR>(grid, g, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s)
+static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const DGArgs &a, hipStream_t s) {
     if (g.grouped) {
-        if (unroll <= 4) KD_DG(1, 4, true); else KD_DG(1, 8, true);
+        if (unroll <= 4) launch_dg<DT, 1, 4, true>(grid, a, s);
+        else launch_dg<DT, 1, 8, true>(grid, a, s);
     } else if (g.tiles == 1) {
-        if (unroll <= 4) KD_DG(1, 4, false); else if (unroll >= 16) KD_DG(1, 16, false); else KD_DG(1, 8, false);
+        if (unroll <= 4) launch_dg<DT, 1, 4, false>(grid, a, s);
+        else if (unroll >= 16) launch_dg<DT, 1, 16, false>(grid, a, s);
+        else launch_dg<DT, 1, 8, false>(grid, a, s);
     } else if (g.tiles == 2) {
-        if (unroll <= 4) KD_DG(2, 4, false); else KD_DG(2, 8, false);
+        if (unroll <= 4) launch_dg<DT, 2, 4, false>(grid, a, s);
+        else launch_dg<DT, 2, 8, false>(grid, a, s);
     } else {
-        if (unroll <= 2) KD_DG(4, 2, false); else KD_DG(4, 4, false);
+        if (unroll <= 2) launch_dg<DT, 4, 2, false>(grid, a, s);
+        else launch_dg<DT, 4, 4, false>(grid, a, s);
     }
-#undef KD_DG
 }
 
-int launch_draw_gather(kerdock_dtype dt, const void *table, int pitch, const float *X, int batch, int n,
-                       int k, int64_t L, const uint32_t *signs, uint64_t seed, int64_t t0, int J, int K,
-                       int chunk, int unroll, float *partial, uint32_t *dbg_samples, float *dbg_coef,
-                       hipStream_t s) {
-    if (chunk < 1 || chunk > MAX_CHUNK) return fail(KERDOCK_ERR_INVALID_ARG, "gather chunk out of range");
-    const GatherShape g = gather_shape(dt, pitch);
-    const int cpb = (J + chunk - 1) / chunk;
-    const int N = J * K;
-    dim3 grid(K * cpb, g.segs, batch);
+int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int unroll, hipStream_t s) {
+    if (a.chunk < 1 || a.chunk > MAX_CHUNK) return fail(KERDOCK_ERR_INVALID_ARG, "gather chunk out of range");
+    const GatherShape g = gather_shape(dt, a.pitch);
+    dim3 grid(K * a.chunks_per_batch, g.segs, batch);
     switch (dt) {
-    case KERDOCK_F32:
-        launch_dt<KERDOCK_F32>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
-        break;
-    case KERDOCK_BF16:
-        launch_dt<KERDOCK_BF16>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
-        break;
-    case KERDOCK_FP8E4M3:
-        launch_dt<KERDOCK_FP8E4M3>(grid, g, unroll, table, X, n, k, L, signs, seed, t0, N, J, chunk, cpb, pitch, partial, dbg_samples, dbg_coef, s);
-        break;
+    case KERDOCK_F32: launch_dt<KERDOCK_F32>(grid, g, unroll, a, s); break;
+    case KERDOCK_BF16: launch_dt<KERDOCK_BF16>(grid, g, unroll, a, s); break;
+    case KERDOCK_FP8E4M3: launch_dt<KERDOCK_FP8E4M3>(grid, g, unroll, a, s); break;
     }
     KD_LAUNCH("k_draw_gather");
     return KERDOCK_OK;
 }
 
-int launch_select(const float *partial, int batch, int m, int pitch, int K, int cpb, int J,
-                  const float *scales, int s_max, float tau, float *mu_out, int32_t *surv,
-                  int32_t *nsurv, hipStream_t s) {
-    const size_t shmem = (size_t)m * sizeof(uint32_t);
+int launch_select(const SelArgs &a, int batch, hipStream_t s) {
+    const size_t shmem = (size_t)a.m * sizeof(uint32_t);
     dim3 grid(batch), block(SELECT_THREADS);
-#define KD_SEL(KM)                                                                            \
-    hipLaunchKernelGGL(k_select<KM>, grid, block, shmem, s, partial, m, pitch, K, cpb, J, scales, \
-                       s_max, tau, mu_out, surv, nsurv)
-    if (K <= 1) KD_SEL(1);
-    else if (K <= 2) KD_SEL(2);
-    else if (K <= 4) KD_SEL(4);
-    else if (K <= 8) KD_SEL(8);
-    else if (K <= 16) KD_SEL(16);
-    else KD_SEL(32);
-#undef KD_SEL
+    if (a.K <= 1) hipLaunchKernelGGL(k_select<1>, grid, block, shmem, s, a);
+    else if (a.K <= 2) hipLaunchKernelGGL(k_select<2>, grid, block, shmem, s, a);
+    else if (a.K <= 4) hipLaunchKernelGGL(k_select<4>, grid, block, shmem, s, a);
+    else if (a.K <= 8) hipLaunchKernelGGL(k_select<8>, grid, block, shmem, s, a);
+    else if (a.K <= 16) hipLaunchKernelGGL(k_select<16>, grid, block, shmem, s, a);
+    else hipLaunchKernelGGL(k_select<32>, grid, block, shmem, s, a);
     KD_LAUNCH("k_select");
     return KERDOCK_OK;
 }
 
-int launch_survivors(const float *A, int n, const float *X, int batch, const int32_t *surv,
-                     const int32_t *nsurv, int s_max, float eps, int32_t *out_idx, float *out_val,
-                     int32_t *out_cnt, float *dbg_values, hipStream_t s) {
-    hipLaunchKernelGGL(k_survivors, dim3(batch), dim3(256), (size_t)s_max * sizeof(float), s, A, n,
-                       X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, dbg_values);
+int launch_survivors(const SurvArgs &a, int batch, hipStream_t s) {
+    hipLaunchKernelGGL(k_survivors, dim3(batch), dim3(SURV_THREADS), (size_t)a.s_max * sizeof(float), s, a);
     KD_LAUNCH("k_survivors");
     return KERDOCK_OK;
 }

@@ -86,6 +86,13 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t byte) {
     return (byte & 0x80u) ? -mag : mag;
 }
 
+// geometry of the gather for one table: bytes per column, 4 KiB tiles per
+// workgroup, segments per column, and the draw groups of short columns
+struct GatherShape {
+    int col_bytes, tiles, segs, groups, tpc, grouped;
+};
+GatherShape gather_shape(kerdock_dtype dt, int pitch);
+
 }  // namespace kd
 
 // --------------------------------------------------------------- handle --
@@ -105,4 +112,6 @@ struct kerdock_handle_s {
     void *ws = nullptr;           // growable workspace of the streaming step
     size_t ws_bytes = 0;
     hipEvent_t ev[5] = {};        // kernel timing events (created on first use)
+    int tune_chunk = 0;           // draws per gather workgroup (0: default)
+    int tune_unroll = 0;          // draws in flight per thread (0: default)
 };

@@ -57,6 +57,26 @@ EXPORTS = {
     "kerdock_debug_signs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "kerdock_row_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kerdock_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kerdock_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]),
+    "kerdock_multi_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ApplyParams), ctypes.c_float,
+                                            ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_void_p)]),
+    "kerdock_multi_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_multi_set_position": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "kerdock_multi_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_multi_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]),
+    "kerdock_multi_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kerdock_sparse_apply_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int),
+                                                  ctypes.POINTER(ApplyParams), ctypes.c_float,
+                                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_void_p),
+                                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                                  ctypes.c_void_p]),
     "kerdock_last_error": (ctypes.c_char_p, []),
 }
 
@@ -210,3 +230,97 @@ def kerdock_row_scales(h, stream=None):
     out = torch.empty((h.m,), dtype=torch.float32, device="cuda")
     _check(lib().kerdock_row_scales(h.ptr, _ptr(out), _stream(stream)))
     return out
+
+
+def kerdock_autotune(h, X, J, K, stream=None):
+    """Time the gather shapes on X and keep the fastest in the handle.
+    Returns (chunk, unroll, ms)."""
+    c, u, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(lib().kerdock_autotune(h.ptr, _dev(X, torch.float32, "X"), X.shape[0], J, K, _stream(stream),
+                                  ctypes.byref(c), ctypes.byref(u), ctypes.byref(ms)))
+    return c.value, u.value, ms.value
+
+
+def _arr(ctype, vals):
+    return (ctype * len(vals))(*vals)
+
+
+class MultiPlan:
+    """Batched form: several handles streamed in one persistent launch.
+    Owns the output tensors it binds (idx, val, cnt per handle)."""
+
+    def __init__(self, ptr, handles, Xs, outs):
+        self.ptr = ptr
+        self.handles = handles       # keep the handles and bound tensors alive
+        self.Xs = Xs
+        self.outs = outs
+
+    def destroy(self):
+        if self.ptr:
+            _check(lib().kerdock_multi_destroy(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def _multi_args(handles, Xs, params, s_max, outs):
+    nh = len(handles)
+    if outs is None:
+        outs = [(torch.empty((X.shape[0], sm), dtype=torch.int32, device=X.device),
+                 torch.empty((X.shape[0], sm), dtype=torch.float32, device=X.device),
+                 torch.empty((X.shape[0],), dtype=torch.int32, device=X.device))
+                for X, sm in zip(Xs, s_max)]
+    ps = (ApplyParams * nh)()
+    for q, p in enumerate(params):
+        ps[q] = ApplyParams(J=p["J"], K=p["K"], seed=p.get("seed", 0), t0=p.get("t0", 0),
+                            tau=p.get("tau", 0.0))
+    hs = _arr(ctypes.c_void_p, [h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in handles])
+    xp = _arr(ctypes.c_void_p, [_dev(X, torch.float32, "X").value for X in Xs])
+    bt = _arr(ctypes.c_int, [X.shape[0] for X in Xs])
+    sm = _arr(ctypes.c_int, list(s_max))
+    oi = _arr(ctypes.c_void_p, [_dev(o[0], torch.int32, "idx").value for o in outs])
+    ov = _arr(ctypes.c_void_p, [_dev(o[1], torch.float32, "val").value for o in outs])
+    oc = _arr(ctypes.c_void_p, [_dev(o[2], torch.int32, "cnt").value for o in outs])
+    return nh, hs, xp, bt, ps, sm, oi, ov, oc, outs
+
+
+def kerdock_multi_create(handles, Xs, params, eps, s_max, outs=None):
+    """Bind per-handle inputs X[q], parameters (dicts with J, K, seed, t0, tau)
+    and outputs into a plan; returns a MultiPlan (outputs in plan.outs)."""
+    nh, hs, xp, bt, ps, sm, oi, ov, oc, outs = _multi_args(handles, Xs, params, s_max, outs)
+    out = ctypes.c_void_p()
+    _check(lib().kerdock_multi_create(hs, nh, xp, bt, ps, float(eps), sm, oi, ov, oc, ctypes.byref(out)))
+    return MultiPlan(out, list(handles), list(Xs), outs)
+
+
+def kerdock_multi_run(plan, stream=None):
+    _check(lib().kerdock_multi_run(plan.ptr, _stream(stream)))
+
+
+def kerdock_multi_set_position(plan, t0s):
+    _check(lib().kerdock_multi_set_position(plan.ptr, _arr(ctypes.c_int64, list(t0s))))
+
+
+def kerdock_multi_graph_launch(plan, stream=None):
+    _check(lib().kerdock_multi_graph_launch(plan.ptr, _stream(stream)))
+
+
+def kerdock_multi_autotune(plan, stream=None):
+    u = ctypes.c_int()
+    _check(lib().kerdock_multi_autotune(plan.ptr, _stream(stream), ctypes.byref(u)))
+    return u.value
+
+
+def kerdock_multi_destroy(plan):
+    plan.destroy()
+
+
+def kerdock_sparse_apply_multi(handles, Xs, params, eps, s_max, outs=None, stream=None):
+    """One-shot batched call; returns [(idx, val, cnt)] per handle."""
+    nh, hs, xp, bt, ps, sm, oi, ov, oc, outs = _multi_args(handles, Xs, params, s_max, outs)
+    _check(lib().kerdock_sparse_apply_multi(hs, nh, xp, bt, ps, float(eps), sm, oi, ov, oc, _stream(stream)))
+    return outs
