@@ -219,6 +219,73 @@ int kerdock_sparse_apply_multi(const kerdock_handle *hs, int nh, const float *co
                                int32_t *const *out_idx, float *const *out_val, int32_t *const *out_cnt,
                                void *stream);
 
+/* ----------------------------------------------------------------------- */
+/* Learned-proposal form.                                                   */
+/* ----------------------------------------------------------------------- */
+
+typedef struct kerdock_mlp_s *kerdock_mlp;
+
+/*
+ * kerdock_mlp_create -- an MLP z = W3 relu(W2 relu(W1 f + b1) + b2) + b3 with
+ * d_in -> h1 -> h2 -> d_out units (each in [1, 16384]) that proposes the rows
+ * of h_eps(Ax) from the basis coefficients f of x.  FP32 master parameters
+ * (He-uniform weights from `seed`, zero biases), a BF16 copy for the GEMMs
+ * (FP32 accumulation), Adam state.  Lives on the current device.
+ * Parameter layout (kerdock_mlp_get_params): W1 [h1][d_in], b1 [h1],
+ * W2 [h2][h1], b2 [h2], W3 [d_out][h2], b3 [d_out], FP32, concatenated.
+ */
+int kerdock_mlp_create(int d_in, int h1, int h2, int d_out, uint64_t seed, kerdock_mlp *out);
+int kerdock_mlp_param_count(kerdock_mlp net, size_t *count);
+/* host <-> device copies of the FP32 parameters; set also refreshes the BF16
+ * copy and resets the Adam state.  Synchronous. */
+int kerdock_mlp_get_params(kerdock_mlp net, float *host);
+int kerdock_mlp_set_params(kerdock_mlp net, const float *host);
+
+/* kerdock_mlp_forward -- logits Z [B][d_out] (device, FP32) from features
+ * F [B][d_in] (device, FP32, rounded to BF16 as GEMM input). */
+int kerdock_mlp_forward(kerdock_mlp net, const float *F, int B, float *Z, void *stream);
+
+/*
+ * kerdock_mlp_train_step -- one step of binary cross-entropy with logits
+ * against labels Y [B][d_out] (device, uint8 0/1) with positive weight
+ * pos_weight: loss = mean over all entries of
+ * -[w+ y log s(z) + (1 - y) log(1 - s(z))], written to loss (device [1]).
+ * Backward with BF16 GEMM inputs (activations and gradients rounded at the
+ * GEMM boundaries) and FP32 accumulation; gradients in the parameter layout
+ * are copied to grads (device, optional); if lr > 0 an Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) updates the parameters.
+ */
+int kerdock_mlp_train_step(kerdock_mlp net, const float *F, const uint8_t *Y, int B, float lr,
+                           float pos_weight, float *loss, float *grads, void *stream);
+int kerdock_mlp_destroy(kerdock_mlp net);
+
+/* kerdock_features -- F [B][d] = H_d x / sqrt(d) (x zero-padded to d): the
+ * coefficients of x in the first Kerdock basis (M_0 = 0, Section 3), the
+ * input of the proposal network.  X device [B][n], F device [B][d]. */
+int kerdock_features(kerdock_handle h, const float *X, int B, float *F, void *stream);
+
+/* kerdock_learned_attach -- use `net` (d_in = d, d_out = m) as the row
+ * proposer of handle h; builds G = A^T A (FP32) once.  The network must
+ * outlive the attachment.  Synchronous. */
+int kerdock_learned_attach(kerdock_handle h, kerdock_mlp net);
+
+/*
+ * kerdock_learned_apply -- h_eps(Ax) with the learned proposal: features,
+ * logits, C = the s_max rows of largest logit, exact a_i.x on C (compensated
+ * dot product), threshold at eps; then the exact energy |Ax|^2 = x^T G x is
+ * compared with the verified energy sum_{i in C} (a_i.x)^2 and every row
+ * whose verified energy falls short by more than eps^2 / 2 is recomputed by
+ * the plain streaming step of kerdock_sparse_apply with parameters p (a row
+ * of h_eps(Ax) outside C removes at least eps^2 from the verified energy, so
+ * no such row is accepted without the fallback).  fallback (device [B]
+ * int32) receives 1 for the recomputed rows.  Outputs as in
+ * kerdock_sparse_apply.  Errors: NOT_PREPARED (no attached network),
+ * INVALID_ARG, OOM, HIP.
+ */
+int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, int s_max,
+                          const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                          int32_t *out_cnt, int32_t *fallback, void *stream);
+
 /* kerdock_query -- geometry of a handle; `info` is host memory. */
 int kerdock_query(kerdock_handle h, kerdock_info *info);
 

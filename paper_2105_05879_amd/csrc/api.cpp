@@ -112,6 +112,7 @@ static void free_handle(kerdock_handle_s *h) {
     (void)hipFree(h->ws);
     for (int q = 0; q < 5; ++q)
         if (h->ev[q]) (void)hipEventDestroy(h->ev[q]);
+    free_learned(h->learned);
     delete h;
 }
 
@@ -140,11 +141,165 @@ static void cache_store(const kerdock_handle_s *h, int K) {
     fclose(f);
 }
 
+// The streaming step for every row of X; rows t with active[t] == 0 (when
+// active is given) are skipped by every kernel and their outputs untouched.
+int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                   const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
+                   const int32_t *active, void *stream) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!p) return fail(KERDOCK_ERR_INVALID_ARG, "params is NULL");
+    if (batch < 0) return fail(KERDOCK_ERR_INVALID_ARG, "batch < 0");
+    if (!(eps > 0.f) || !isfinite(eps)) return fail(KERDOCK_ERR_INVALID_ARG, "eps must be > 0");
+    if (s_max < 1 || s_max > h->m) return fail(KERDOCK_ERR_INVALID_ARG, "s_max must lie in [1, m]");
+    if (p->J < 1 || p->K < 1 || p->K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "need J >= 1, 1 <= K <= 32");
+    if ((int64_t)p->J * p->K > ((int64_t)1 << 31) - 64)
+        return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
+    if (batch == 0) return KERDOCK_OK;
+    if (!X || !out_idx || !out_val || !out_cnt)
+        return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int J = p->J, K = p->K, N = J * K;
+
+    const Workspace lay = workspace_layout(h, batch, J, K, s_max);
+    int rc = ensure_workspace(h, lay.total);
+    if (rc != KERDOCK_OK) return rc;
+    char *ws = reinterpret_cast<char *>(h->ws);
+    float *partial = reinterpret_cast<float *>(ws + lay.partial);
+    int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
+    int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
+    const int chunk = gather_chunk(h, J);
+    const int cpb = (J + chunk - 1) / chunk;
+    if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
+        return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
+
+    // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
+    // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
+    const bool timed = p->kernel_ms != nullptr;
+    if (timed && !h->ev[0])
+        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
+    if (timed) KD_HIP(hipEventRecord(h->ev[1], s));
+    DGArgs dg{};
+    dg.table = reinterpret_cast<const unsigned char *>(h->table);
+    dg.col_bytes = h->pitch * (int)dtype_bytes(h->dtype);
+    dg.X = X;
+    dg.n = h->n;
+    dg.k = h->k;
+    dg.L = h->L;
+    dg.signs = h->signs;
+    dg.seed = p->seed;
+    dg.t0_dev = nullptr;
+    dg.t0 = p->t0;
+    dg.N = N;
+    dg.J = J;
+    dg.chunk = chunk;
+    dg.chunks_per_batch = cpb;
+    {
+        const GatherShape gs = gather_shape(h->dtype, h->pitch);
+        dg.groups = gs.groups;
+        dg.tpc = gs.tpc;
+    }
+    dg.pitch = h->pitch;
+    dg.partial = partial;
+    dg.dbg_samples = p->dbg_samples;
+    dg.dbg_coef = p->dbg_coef;
+    dg.active = active;
+    rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
+    SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, active};
+    if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
+    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr};
+    if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
+    if (rc != KERDOCK_OK) return rc;
+    if (timed) {
+        KD_HIP(hipEventSynchronize(h->ev[4]));
+        p->kernel_ms[0] = 0.f;
+        for (int q = 1; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
+    }
+    if (p->dbg_survivors)
+        KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
+    return KERDOCK_OK;
+}
+
 }  // namespace kd
 
 using namespace kd;
 
 extern "C" {
+
+int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, void *stream,
+                     int *best_chunk, int *best_unroll, float *best_ms) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!X || batch < 1 || J < 1 || K < 1 || K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "autotune: bad arguments");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const GatherShape gs = gather_shape(h->dtype, h->pitch);
+    std::vector<int> unrolls;
+    if (gs.grouped) unrolls = {4, 8};
+    else if (gs.tiles == 1) unrolls = {4, 8, 16};
+    else if (gs.tiles == 2) unrolls = {4, 8};
+    else unrolls = {2, 4};
+    const int chunks[] = {256, 512, 1024};
+    size_t need = 0;
+    for (int c : chunks) {
+        const size_t cc = std::min(c, J);
+        need = std::max(need, (size_t)batch * K * ((J + cc - 1) / cc) * h->pitch * 4);
+    }
+    int rc = ensure_workspace(h, need);
+    if (rc != KERDOCK_OK) return rc;
+    if (!h->ev[0])
+        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
+    float best = 1e30f;
+    int bc = 512, bu = 8;
+    for (int c : chunks) {
+        const int chunk = std::min(c, J);
+        if (c > J && c != chunks[0]) continue;
+        for (int u : unrolls) {
+            DGArgs dg{};
+            dg.table = reinterpret_cast<const unsigned char *>(h->table);
+            dg.col_bytes = gs.col_bytes;
+            dg.X = X;
+            dg.n = h->n;
+            dg.k = h->k;
+            dg.L = h->L;
+            dg.signs = h->signs;
+            dg.seed = 12345;
+            dg.t0 = 0;
+            dg.N = J * K;
+            dg.J = J;
+            dg.chunk = chunk;
+            dg.chunks_per_batch = (J + chunk - 1) / chunk;
+            dg.groups = gs.groups;
+            dg.tpc = gs.tpc;
+            dg.pitch = h->pitch;
+            dg.partial = reinterpret_cast<float *>(h->ws);
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                KD_HIP(hipEventRecord(h->ev[0], s));
+                rc = launch_draw_gather(h->dtype, dg, batch, K, u, s);
+                if (rc != KERDOCK_OK) return rc;
+                KD_HIP(hipEventRecord(h->ev[1], s));
+                KD_HIP(hipEventSynchronize(h->ev[1]));
+                float ms = 0.f;
+                KD_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+                if (rep > 0) tmin = std::min(tmin, ms);     // first run warms up
+            }
+            if (tmin < best) {
+                best = tmin;
+                bc = chunk;
+                bu = u;
+            }
+        }
+    }
+    h->tune_chunk = bc;
+    h->tune_unroll = bu;
+    cache_store(h, K);
+    if (best_chunk) *best_chunk = bc;
+    if (best_unroll) *best_unroll = bu;
+    if (best_ms) *best_ms = best;
+    return KERDOCK_OK;
+}
+
 
 const char *kerdock_last_error(void) { return g_error.c_str(); }
 
@@ -231,151 +386,7 @@ int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max) {
 int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps, int s_max,
                          const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
                          int32_t *out_cnt, void *stream) {
-    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
-    if (!p) return fail(KERDOCK_ERR_INVALID_ARG, "params is NULL");
-    if (batch < 0) return fail(KERDOCK_ERR_INVALID_ARG, "batch < 0");
-    if (!(eps > 0.f) || !isfinite(eps)) return fail(KERDOCK_ERR_INVALID_ARG, "eps must be > 0");
-    if (s_max < 1 || s_max > h->m) return fail(KERDOCK_ERR_INVALID_ARG, "s_max must lie in [1, m]");
-    if (p->J < 1 || p->K < 1 || p->K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "need J >= 1, 1 <= K <= 32");
-    if ((int64_t)p->J * p->K > ((int64_t)1 << 31) - 64)
-        return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
-    if (batch == 0) return KERDOCK_OK;
-    if (!X || !out_idx || !out_val || !out_cnt)
-        return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int J = p->J, K = p->K, N = J * K;
-
-    const Workspace lay = workspace_layout(h, batch, J, K, s_max);
-    int rc = ensure_workspace(h, lay.total);
-    if (rc != KERDOCK_OK) return rc;
-    char *ws = reinterpret_cast<char *>(h->ws);
-    float *partial = reinterpret_cast<float *>(ws + lay.partial);
-    int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
-    int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
-    const int chunk = gather_chunk(h, J);
-    const int cpb = (J + chunk - 1) / chunk;
-    if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
-        return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
-
-    // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
-    // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
-    const bool timed = p->kernel_ms != nullptr;
-    if (timed && !h->ev[0])
-        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
-    if (timed) KD_HIP(hipEventRecord(h->ev[1], s));
-    DGArgs dg{};
-    dg.table = reinterpret_cast<const unsigned char *>(h->table);
-    dg.col_bytes = h->pitch * (int)dtype_bytes(h->dtype);
-    dg.X = X;
-    dg.n = h->n;
-    dg.k = h->k;
-    dg.L = h->L;
-    dg.signs = h->signs;
-    dg.seed = p->seed;
-    dg.t0_dev = nullptr;
-    dg.t0 = p->t0;
-    dg.N = N;
-    dg.J = J;
-    dg.chunk = chunk;
-    dg.chunks_per_batch = cpb;
-    {
-        const GatherShape gs = gather_shape(h->dtype, h->pitch);
-        dg.groups = gs.groups;
-        dg.tpc = gs.tpc;
-    }
-    dg.pitch = h->pitch;
-    dg.partial = partial;
-    dg.dbg_samples = p->dbg_samples;
-    dg.dbg_coef = p->dbg_coef;
-    rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
-    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
-    SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv};
-    if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
-    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
-    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values};
-    if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
-    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
-    if (rc != KERDOCK_OK) return rc;
-    if (timed) {
-        KD_HIP(hipEventSynchronize(h->ev[4]));
-        p->kernel_ms[0] = 0.f;
-        for (int q = 1; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
-    }
-    if (p->dbg_survivors)
-        KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
-    return KERDOCK_OK;
-}
-
-int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, void *stream,
-                     int *best_chunk, int *best_unroll, float *best_ms) {
-    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
-    if (!X || batch < 1 || J < 1 || K < 1 || K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "autotune: bad arguments");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const GatherShape gs = gather_shape(h->dtype, h->pitch);
-    std::vector<int> unrolls;
-    if (gs.grouped) unrolls = {4, 8};
-    else if (gs.tiles == 1) unrolls = {4, 8, 16};
-    else if (gs.tiles == 2) unrolls = {4, 8};
-    else unrolls = {2, 4};
-    const int chunks[] = {256, 512, 1024};
-    size_t need = 0;
-    for (int c : chunks) {
-        const size_t cc = std::min(c, J);
-        need = std::max(need, (size_t)batch * K * ((J + cc - 1) / cc) * h->pitch * 4);
-    }
-    int rc = ensure_workspace(h, need);
-    if (rc != KERDOCK_OK) return rc;
-    if (!h->ev[0])
-        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
-    float best = 1e30f;
-    int bc = 512, bu = 8;
-    for (int c : chunks) {
-        const int chunk = std::min(c, J);
-        if (c > J && c != chunks[0]) continue;
-        for (int u : unrolls) {
-            DGArgs dg{};
-            dg.table = reinterpret_cast<const unsigned char *>(h->table);
-            dg.col_bytes = gs.col_bytes;
-            dg.X = X;
-            dg.n = h->n;
-            dg.k = h->k;
-            dg.L = h->L;
-            dg.signs = h->signs;
-            dg.seed = 12345;
-            dg.t0 = 0;
-            dg.N = J * K;
-            dg.J = J;
-            dg.chunk = chunk;
-            dg.chunks_per_batch = (J + chunk - 1) / chunk;
-            dg.groups = gs.groups;
-            dg.tpc = gs.tpc;
-            dg.pitch = h->pitch;
-            dg.partial = reinterpret_cast<float *>(h->ws);
-            float tmin = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                KD_HIP(hipEventRecord(h->ev[0], s));
-                rc = launch_draw_gather(h->dtype, dg, batch, K, u, s);
-                if (rc != KERDOCK_OK) return rc;
-                KD_HIP(hipEventRecord(h->ev[1], s));
-                KD_HIP(hipEventSynchronize(h->ev[1]));
-                float ms = 0.f;
-                KD_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-                if (rep > 0) tmin = std::min(tmin, ms);     // first run warms up
-            }
-            if (tmin < best) {
-                best = tmin;
-                bc = chunk;
-                bu = u;
-            }
-        }
-    }
-    h->tune_chunk = bc;
-    h->tune_unroll = bu;
-    cache_store(h, K);
-    if (best_chunk) *best_chunk = bc;
-    if (best_unroll) *best_unroll = bu;
-    if (best_ms) *best_ms = best;
-    return KERDOCK_OK;
+    return kd::apply_internal(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, nullptr, stream);
 }
 
 int kerdock_query(kerdock_handle h, kerdock_info *info) {

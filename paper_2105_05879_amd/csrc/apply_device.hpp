@@ -134,6 +134,7 @@ struct DGArgs {
     float *partial;           // [batch][K chunks_per_batch][pitch]
     uint32_t *dbg_samples;    // optional [batch][N]
     float *dbg_coef;          // optional [batch][N]
+    const int32_t *active;    // optional [batch]: vectors with 0 are skipped
 };
 
 template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
@@ -151,6 +152,7 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     uint32_t *__restrict__ dbg_samples = a.dbg_samples;
     float *__restrict__ dbg_coef = a.dbg_coef;
     constexpr int E = Elems<DT>::N;
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
     const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
     const int jbeg = kb * J + cj * chunk;
     const int cnt = min(chunk, (kb + 1) * J - jbeg);
@@ -358,74 +360,14 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh) 
     return res;
 }
 
-// Inputs and outputs of the selection for one handle.
-struct SelArgs {
-    const float *partial;
-    int m, pitch, K, chunks_per_batch, J;
-    const float *scales;
-    int s_max;
-    float tau;
-    float *mu_out;            // optional [batch][m]
-    int32_t *surv;            // [batch][s_max]
-    int32_t *nsurv;           // [batch]
-};
-
-// shared memory: key[m], hist[256], scan_sh[SELECT_THREADS/64 + 1], sel_state[2]
-template <int KMAX>
-__device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *key, uint32_t *hist,
+// The s_max largest keys (ties: smaller index), optionally only keys >=
+// tau_bits, written in ascending index order to surv_row (padded with -1),
+// their number to *nsurv_out.  Radix select over the 32-bit keys in LDS
+// (8 bits per round, histogram in LDS), then two block-wide scans.
+__device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max, uint32_t tau_bits,
+                                           int32_t *surv_row, int32_t *nsurv_out, uint32_t *hist,
                                            int *scan_sh, uint32_t *sel_state) {
-    const float *__restrict__ partial = a.partial;
-    const int m = a.m, pitch = a.pitch, K = a.K, chunks_per_batch = a.chunks_per_batch, J = a.J;
-    const int s_max = a.s_max;
-    const float tau = a.tau;
-    const float *__restrict__ scales = a.scales;
-    float *__restrict__ mu_out = a.mu_out;
-    int32_t *__restrict__ surv = a.surv;
-    int32_t *__restrict__ nsurv = a.nsurv;
     uint32_t &sel_prefix = sel_state[0], &sel_want = sel_state[1];
-    const int nchunks = K * chunks_per_batch;
-    const float *pt = partial + (size_t)t * nchunks * pitch;
-    for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
-        float v[KMAX];
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            float s = INFINITY;
-            if (a < K) {
-                s = 0.f;
-                for (int c = 0; c < chunks_per_batch; ++c)
-                    s += pt[(size_t)(a * chunks_per_batch + c) * pitch + i];
-                s = s / (float)J;
-            }
-            v[a] = s;
-        }
-        // bitonic sort, ascending
-#pragma unroll
-        for (int size = 2; size <= KMAX; size <<= 1)
-#pragma unroll
-            for (int stride = size >> 1; stride > 0; stride >>= 1)
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a) {
-                    const int bb = a ^ stride;
-                    if (bb > a) {
-                        const bool up = (a & size) == 0;
-                        const float lo = fminf(v[a], v[bb]), hi = fmaxf(v[a], v[bb]);
-                        v[a] = up ? lo : hi;
-                        v[bb] = up ? hi : lo;
-                    }
-                }
-        float lo_mid = 0.f, hi_mid = 0.f;
-#pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            if (a == (K - 1) / 2) lo_mid = v[a];
-            if (a == K / 2) hi_mid = v[a];
-        }
-        float med = (K & 1) ? hi_mid : 0.5f * (lo_mid + hi_mid);
-        med *= scales[i];
-        if (mu_out) mu_out[(size_t)t * m + i] = med;
-        key[i] = __float_as_uint(fabsf(med));
-    }
-    __syncthreads();
-
     // radix select of the s_max-th largest key
     uint32_t prefix = 0, fixed = 0, want = (uint32_t)s_max;
     const bool take_all = s_max >= m;
@@ -472,7 +414,6 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
         }
     }
     const uint32_t theta = prefix;
-    const uint32_t tau_bits = __float_as_uint(fmaxf(tau, 0.f));
 
     // ascending compaction: thread owns rows [i0, i1)
     const int per = (m + SELECT_THREADS - 1) / SELECT_THREADS;
@@ -502,12 +443,85 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
             bool sel = take_all || kk > theta || (kk == theta && (uint32_t)er < want);
             if (!take_all && kk == theta) ++er;
             sel = sel && kk >= tau_bits;
-            if (sel && pos < s_max) surv[(size_t)t * s_max + pos++] = i;
+            if (sel && pos < s_max) surv_row[pos++] = i;
         }
     }
     total = min(total, s_max);
-    for (int s = total + threadIdx.x; s < s_max; s += SELECT_THREADS) surv[(size_t)t * s_max + s] = -1;
-    if (threadIdx.x == 0) nsurv[t] = total;
+    for (int s = total + threadIdx.x; s < s_max; s += SELECT_THREADS) surv_row[s] = -1;
+    if (threadIdx.x == 0) *nsurv_out = total;
+}
+
+
+// Inputs and outputs of the selection for one handle.
+struct SelArgs {
+    const float *partial;
+    int m, pitch, K, chunks_per_batch, J;
+    const float *scales;
+    int s_max;
+    float tau;
+    float *mu_out;            // optional [batch][m]
+    int32_t *surv;            // [batch][s_max]
+    int32_t *nsurv;           // [batch]
+    const int32_t *active;    // optional [batch]: vectors with 0 are skipped
+};
+
+// shared memory: key[m], hist[256], scan_sh[SELECT_THREADS/64 + 1], sel_state[2]
+template <int KMAX>
+__device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *key, uint32_t *hist,
+                                           int *scan_sh, uint32_t *sel_state) {
+    const float *__restrict__ partial = a.partial;
+    const int m = a.m, pitch = a.pitch, K = a.K, chunks_per_batch = a.chunks_per_batch, J = a.J;
+    const int s_max = a.s_max;
+    const float tau = a.tau;
+    const float *__restrict__ scales = a.scales;
+    float *__restrict__ mu_out = a.mu_out;
+    int32_t *__restrict__ surv = a.surv;
+    int32_t *__restrict__ nsurv = a.nsurv;
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
+    const int nchunks = K * chunks_per_batch;
+    const float *pt = partial + (size_t)t * nchunks * pitch;
+    for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
+        float v[KMAX];
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) {
+            float s = INFINITY;
+            if (a < K) {
+                s = 0.f;
+                for (int c = 0; c < chunks_per_batch; ++c)
+                    s += pt[(size_t)(a * chunks_per_batch + c) * pitch + i];
+                s = s / (float)J;
+            }
+            v[a] = s;
+        }
+        // bitonic sort, ascending
+#pragma unroll
+        for (int size = 2; size <= KMAX; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                for (int a = 0; a < KMAX; ++a) {
+                    const int bb = a ^ stride;
+                    if (bb > a) {
+                        const bool up = (a & size) == 0;
+                        const float lo = fminf(v[a], v[bb]), hi = fmaxf(v[a], v[bb]);
+                        v[a] = up ? lo : hi;
+                        v[bb] = up ? hi : lo;
+                    }
+                }
+        float lo_mid = 0.f, hi_mid = 0.f;
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) {
+            if (a == (K - 1) / 2) lo_mid = v[a];
+            if (a == K / 2) hi_mid = v[a];
+        }
+        float med = (K & 1) ? hi_mid : 0.5f * (lo_mid + hi_mid);
+        med *= scales[i];
+        if (mu_out) mu_out[(size_t)t * m + i] = med;
+        key[i] = __float_as_uint(fabsf(med));
+    }
+    __syncthreads();
+    select_top(key, m, s_max, __float_as_uint(fmaxf(tau, 0.f)), surv + (size_t)t * s_max, nsurv + t, hist,
+               scan_sh, sel_state);
 }
 
 // ------------------------------------------------------------- survivors --
@@ -533,6 +547,8 @@ struct SurvArgs {
     float *out_val;
     int32_t *out_cnt;
     float *dbg_values;        // optional [batch][s_max]
+    const int32_t *active;    // optional [batch]: vectors with 0 are skipped
+    float *vsum2;             // optional [batch]: sum over S of (a_i.x)^2
 };
 
 constexpr int SURV_THREADS = 256;
@@ -550,6 +566,7 @@ __device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *v
     float *__restrict__ out_val = a.out_val;
     int32_t *__restrict__ out_cnt = a.out_cnt;
     float *__restrict__ dbg_values = a.dbg_values;
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ns = min(nsurv[t], s_max);
     const float *x = X + (size_t)t * n;
@@ -596,6 +613,13 @@ __device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *v
     }
     if (dbg_values)
         for (int s = lane; s < s_max; s += 64) dbg_values[(size_t)t * s_max + s] = s < ns ? vals[s] : 0.f;
+    if (a.vsum2) {
+        float e2 = 0.f;
+        for (int s = lane; s < ns; s += 64) e2 += vals[s] * vals[s];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
+        if (lane == 0) a.vsum2[t] = e2;
+    }
     if (lane == 0) out_cnt[t] = base;
 }
 

@@ -28,7 +28,48 @@ __global__ __launch_bounds__(SURV_THREADS) void k_survivors(SurvArgs a) {
     survivors_vec(a, blockIdx.x, vals);
 }
 
+// Learned form: the c rows of largest logit (ties: smaller index), ascending.
+// Keys map floats monotonically to unsigned integers.
+__global__ __launch_bounds__(SELECT_THREADS) void k_topc_logits(const float *__restrict__ Z, int m, int c,
+                                                                int32_t *__restrict__ cand,
+                                                                int32_t *__restrict__ ncand) {
+    extern __shared__ uint32_t key[];
+    __shared__ uint32_t hist[256];
+    __shared__ int scan_sh[SELECT_THREADS / 64 + 1];
+    __shared__ uint32_t sel_state[2];
+    const int t = blockIdx.x;
+    for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
+        const uint32_t u = __float_as_uint(Z[(size_t)t * m + i]);
+        key[i] = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    }
+    __syncthreads();
+    select_top(key, m, c, 0u, cand + (size_t)t * c, ncand + t, hist, scan_sh, sel_state);
+}
+
+// fall back when the verified energy sum_{i in C} (a_i.x)^2 falls short of
+// the exact energy |Ax|^2 by more than tol (NaN also falls back)
+__global__ void k_fallback_flags(const float *__restrict__ E, const float *__restrict__ vsum2, int B, float tol,
+                                 int32_t *__restrict__ flags) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= B) return;
+    const float gap = E[t] - vsum2[t];
+    flags[t] = (gap <= tol) ? 0 : 1;
+}
+
 // -------------------------------------------------------------- launchers --
+
+int launch_topc_logits(const float *Z, int B, int m, int c, int32_t *cand, int32_t *ncand, hipStream_t s) {
+    hipLaunchKernelGGL(k_topc_logits, dim3(B), dim3(SELECT_THREADS), (size_t)m * 4, s, Z, m, c, cand, ncand);
+    KD_LAUNCH("k_topc_logits");
+    return KERDOCK_OK;
+}
+
+int launch_fallback_flags(const float *E, const float *vsum2, int B, float tol, int32_t *flags, hipStream_t s) {
+    hipLaunchKernelGGL(k_fallback_flags, dim3((B + 255) / 256), dim3(256), 0, s, E, vsum2, B, tol, flags);
+    KD_LAUNCH("k_fallback_flags");
+    return KERDOCK_OK;
+}
+
 
 GatherShape gather_shape(kerdock_dtype dt, int pitch) {
     GatherShape g;

@@ -97,6 +97,11 @@ GatherShape gather_shape(kerdock_dtype dt, int pitch);
 
 // --------------------------------------------------------------- handle --
 
+struct kerdock_learned_s;
+namespace kd {
+void free_learned(kerdock_learned_s *L);
+}
+
 struct kerdock_handle_s {
     int m = 0, n = 0, k = 0, d = 0, pitch = 0;
     int64_t L = 0;
@@ -114,4 +119,5 @@ struct kerdock_handle_s {
     hipEvent_t ev[5] = {};        // kernel timing events (created on first use)
     int tune_chunk = 0;           // draws per gather workgroup (0: default)
     int tune_unroll = 0;          // draws in flight per thread (0: default)
+    kerdock_learned_s *learned = nullptr;   // attached learned-proposal state
 };

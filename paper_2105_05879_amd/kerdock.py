@@ -57,6 +57,23 @@ EXPORTS = {
     "kerdock_debug_signs": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "kerdock_row_scales": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kerdock_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kerdock_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]),
+    "kerdock_mlp_param_count": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "kerdock_mlp_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_mlp_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "kerdock_mlp_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                              ctypes.c_float, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "kerdock_mlp_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kerdock_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "kerdock_learned_attach": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_learned_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                                             ctypes.c_int, ctypes.POINTER(ApplyParams), ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kerdock_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]),
@@ -324,3 +341,90 @@ def kerdock_sparse_apply_multi(handles, Xs, params, eps, s_max, outs=None, strea
     nh, hs, xp, bt, ps, sm, oi, ov, oc, outs = _multi_args(handles, Xs, params, s_max, outs)
     _check(lib().kerdock_sparse_apply_multi(hs, nh, xp, bt, ps, float(eps), sm, oi, ov, oc, _stream(stream)))
     return outs
+
+
+class MLP:
+    """The learned-proposal network (device parameters, Adam state)."""
+
+    def __init__(self, ptr, dims):
+        self.ptr = ptr
+        self.dims = dims
+
+    @property
+    def param_count(self):
+        c = ctypes.c_size_t()
+        _check(lib().kerdock_mlp_param_count(self.ptr, ctypes.byref(c)))
+        return c.value
+
+    def destroy(self):
+        if self.ptr:
+            _check(lib().kerdock_mlp_destroy(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def kerdock_mlp_create(d_in, h1, h2, d_out, seed=0):
+    out = ctypes.c_void_p()
+    _check(lib().kerdock_mlp_create(d_in, h1, h2, d_out, seed, ctypes.byref(out)))
+    return MLP(out, (d_in, h1, h2, d_out))
+
+
+def kerdock_mlp_get_params(net):
+    import numpy as np
+    buf = np.zeros(net.param_count, dtype=np.float32)
+    _check(lib().kerdock_mlp_get_params(net.ptr, buf.ctypes.data_as(ctypes.c_void_p)))
+    return buf
+
+
+def kerdock_mlp_set_params(net, params):
+    import numpy as np
+    buf = np.ascontiguousarray(params, dtype=np.float32)
+    assert buf.size == net.param_count
+    _check(lib().kerdock_mlp_set_params(net.ptr, buf.ctypes.data_as(ctypes.c_void_p)))
+
+
+def kerdock_mlp_forward(net, F, stream=None):
+    Z = torch.empty((F.shape[0], net.dims[3]), dtype=torch.float32, device=F.device)
+    _check(lib().kerdock_mlp_forward(net.ptr, _dev(F, torch.float32, "F"), F.shape[0], _ptr(Z), _stream(stream)))
+    return Z
+
+
+def kerdock_mlp_train_step(net, F, Y, lr, pos_weight, want_grads=False, stream=None):
+    """One training step; returns (loss tensor [1], grads or None)."""
+    loss = torch.empty((1,), dtype=torch.float32, device=F.device)
+    grads = torch.empty((net.param_count,), dtype=torch.float32, device=F.device) if want_grads else None
+    _check(lib().kerdock_mlp_train_step(net.ptr, _dev(F, torch.float32, "F"), _dev(Y, torch.uint8, "Y"),
+                                        F.shape[0], float(lr), float(pos_weight), _ptr(loss), _ptr(grads),
+                                        _stream(stream)))
+    return loss, grads
+
+
+def kerdock_features(h, X, stream=None):
+    F = torch.empty((X.shape[0], h.info.d), dtype=torch.float32, device=X.device)
+    _check(lib().kerdock_features(h.ptr, _dev(X, torch.float32, "X"), X.shape[0], _ptr(F), _stream(stream)))
+    return F
+
+
+def kerdock_learned_attach(h, net):
+    _check(lib().kerdock_learned_attach(h.ptr, net.ptr))
+    h._net = net                      # keep the network alive with the handle
+
+
+def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, stream=None):
+    """Returns (idx, val, cnt, fallback)."""
+    B = X.shape[0]
+    dev = X.device
+    if out is None:
+        out = (torch.empty((B, s_max), dtype=torch.int32, device=dev),
+               torch.empty((B, s_max), dtype=torch.float32, device=dev),
+               torch.empty((B,), dtype=torch.int32, device=dev))
+    fb = torch.empty((B,), dtype=torch.int32, device=dev)
+    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau)
+    _check(lib().kerdock_learned_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max, ctypes.byref(p),
+                                       _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(fb), _stream(stream)))
+    return out[0], out[1], out[2], fb
