@@ -239,6 +239,108 @@ def batched_form(kd, torch, np, workloads, args):
     return res
 
 
+def learned_form(kd, torch, np, workloads, args):
+    """n = 1024 structured dictionary, supports from a pool of 512 size-16
+    patterns: the MLP proposer (1024 -> 512 -> 512 -> 1024) is trained on
+    2^18 (features, support of the plain method's output) pairs with the
+    library's own kernels, then the learned apply (proposal, exact dots,
+    energy check, fallback to the plain method) is timed on 2^14 held-out x
+    against the plain FP32 form, each at its calibrated (J, K)."""
+    n, s_max = 1024, 160
+    pool = workloads.support_pool(n)
+    ntrain, ntest = args.learned_train, args.learned_test
+    wtr = workloads.learned(ntrain, n=n, offset=0, pool=pool)
+    wte = workloads.learned(ntest, n=n, offset=1, pool=pool)
+    wc = workloads.learned(256, n=n, offset=2, pool=pool)
+    A = torch.from_numpy(wtr.A).cuda()
+    Xte = torch.from_numpy(wte.X).cuda()
+    Xc = torch.from_numpy(wc.X).cuda()
+    A64 = wtr.A.astype(np.float64)
+    sup_te, _ = eps_supports(A64, wte.X.astype(np.float64), args.eps)
+    sup_c, _ = eps_supports(A64, wc.X.astype(np.float64), args.eps)
+    res = {"workload": "n=1024 Haar*diag(logU[0.1,10]), supports from 512 size-16 patterns, eps=%g, "
+                       "s_max=%d, %d training pairs, %d held-out x" % (args.eps, s_max, ntrain, ntest)}
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, out
+
+    # plain FP32 form
+    h32 = kd.kerdock_prepare(A, "f32")
+    J32, K32, _ = calibrate(kd, h32, Xc, sup_c, args.eps, s_max, args.recall, args.seed)
+    kd.kerdock_reserve(h32, ntest, J32, K32, s_max)
+    dt, out = timed(lambda: kd.kerdock_sparse_apply(h32, Xte, args.eps, s_max, J32, K32, args.seed))
+    rec = recall_of(out[0].cpu().numpy(), out[2].cpu().numpy(), sup_te)
+    res["plain_f32"] = {"x_per_s": ntest / dt, "ms_per_step": dt * 1e3, "J": J32, "K": K32,
+                        "recall_mean": float(np.mean(rec))}
+    h32.destroy()
+    torch.cuda.empty_cache()
+    log("learned: plain f32 J=%d K=%d %.1f x/s recall %.4f" % (J32, K32, ntest / dt, np.mean(rec)))
+
+    # labels from the plain method (BF16 table), features, training
+    h = kd.kerdock_prepare(A, "bf16")
+    J, K, _ = calibrate(kd, h, Xc, sup_c, args.eps, s_max, args.recall, args.seed)
+    t0 = time.perf_counter()
+    Xtr = torch.from_numpy(wtr.X).cuda()
+    Y = torch.zeros((ntrain, n), dtype=torch.uint8, device="cuda")
+    for b in range(0, ntrain, 8192):
+        idx, val, cnt = kd.kerdock_sparse_apply(h, Xtr[b:b + 8192].contiguous(), args.eps, s_max, J, K,
+                                                args.seed, t0=b)
+        rows = torch.arange(s_max, device="cuda")[None, :] < cnt[:, None]
+        nz = torch.nonzero(rows)
+        Y[b + nz[:, 0], idx[rows].long()] = 1
+    F = kd.kerdock_features(h, Xtr)
+    del Xtr
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    net = kd.kerdock_mlp_create(h.info.d, 512, 512, n, seed=args.seed)
+    pos_w = float(n / max(1.0, Y.float().sum(1).mean().item()))
+    g = torch.Generator(device="cpu").manual_seed(args.seed)
+    t0 = time.perf_counter()
+    steps = 0
+    for epoch in range(args.learned_epochs):
+        perm = torch.randperm(ntrain, generator=g).cuda()
+        for b in range(0, ntrain, 512):
+            sel = perm[b:b + 512]
+            loss, _ = kd.kerdock_mlp_train_step(net, F[sel].contiguous(), Y[sel].contiguous(), 1e-3, pos_w)
+            steps += 1
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del F, Y
+    kd.kerdock_learned_attach(h, net)
+    fb_out = {}
+
+    def learned_step():
+        r = kd.kerdock_learned_apply(h, Xte, args.eps, s_max, J, K, args.seed, t0=1 << 40)
+        fb_out["fb"] = r[3]
+        return r
+    dt, out = timed(learned_step)
+    rec = recall_of(out[0].cpu().numpy(), out[2].cpu().numpy(), sup_te)
+    fb = fb_out["fb"].float().mean().item()
+    res["learned_bf16"] = {"x_per_s": ntest / dt, "ms_per_step": dt * 1e3, "fallback_J": J, "fallback_K": K,
+                           "recall_mean": float(np.mean(rec)), "fallback_rate": fb,
+                           "final_train_loss": loss.item(), "train_steps": steps, "train_s": t_train,
+                           "label_generation_s": t_labels}
+    # the same BF16 table without the proposer, for reference
+    dt2, out2 = timed(lambda: kd.kerdock_sparse_apply(h, Xte, args.eps, s_max, J, K, args.seed))
+    rec2 = recall_of(out2[0].cpu().numpy(), out2[2].cpu().numpy(), sup_te)
+    res["plain_bf16"] = {"x_per_s": ntest / dt2, "ms_per_step": dt2 * 1e3, "J": J, "K": K,
+                         "recall_mean": float(np.mean(rec2))}
+    res["speedup_vs_plain"] = res["learned_bf16"]["x_per_s"] / res["plain_f32"]["x_per_s"]
+    log("learned: %.1f x/s recall %.4f fallback %.3f (train %.1f s, %d steps, loss %.4f); plain bf16 %.1f x/s"
+        % (ntest / dt, np.mean(rec), fb, t_train, steps, loss.item(), ntest / dt2))
+    h.destroy()
+    net.destroy()
+    torch.cuda.empty_cache()
+    return res
+
+
 def dense_baselines(torch, A, X):
     out = {}
     for _ in range(3):
@@ -291,7 +393,8 @@ def traffic_from_profiles(dt):
         if ": " in line:
             k, v = line.strip().split(": ", 1)
             rec[k] = v
-    src = open(os.path.join(ROOT, "paper_2105_05879_amd", "csrc", "apply_kernels.hip"), "rb").read()
+    csrc = os.path.join(ROOT, "paper_2105_05879_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("apply_kernels.hip", "apply_device.hpp"))
     if rec.get("apply_kernels_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return float(rec["hbm_bytes_per_launch"]) if "hbm_bytes_per_launch" in rec else None
@@ -312,6 +415,10 @@ def main():
     ap.add_argument("--K", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
+    ap.add_argument("--learned-train", type=int, default=1 << 18)
+    ap.add_argument("--learned-test", type=int, default=1 << 14)
+    ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of this many MiB (a reference "
                          "kernel of known traffic for hardware counters)")
@@ -360,6 +467,8 @@ def main():
         del A, X, Xc
         torch.cuda.empty_cache()
         forms["batched"] = batched_form(kd, torch, np, workloads, args)
+    if not args.no_learned:
+        forms["learned"] = learned_form(kd, torch, np, workloads, args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A64, X64, head["J"], head["K"], args.eps, args.s_max, args.seed)
@@ -368,7 +477,7 @@ def main():
     roof = {"bound": "hbm", "achieved": head["gather_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": head["gather_frac_hbm"],
             "traffic": traffic_from_profiles(head_dt),
-            "kernel": "k_gather (%s table)" % head_dt,
+            "kernel": "k_draw_gather (%s table)" % head_dt,
             "algorithmic_bytes_per_launch": head["gather_bytes_per_launch"],
             "avg_launch_ms": head["kernel_ms"]["gather"]}
     line = {
