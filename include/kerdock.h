@@ -286,6 +286,20 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
                           const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
                           int32_t *out_cnt, int32_t *fallback, void *stream);
 
+/*
+ * kerdock_theory_params -- the streaming parameters of Theorem 5 for a target
+ * failure probability eta (0 < eta < 1) and x in Sigma(A, s, delta):
+ * gamma = (eps - delta) / 2, J = ceil(4 e^2 |A|_{2->inf}^2 / gamma^2),
+ * K = ceil(2 log(m / eta)), so that |mu - Ax|_inf < gamma with probability
+ * at least 1 - eta; tau = (eps + delta) / 2 (the separation of Section 1)
+ * and |A|_{2->inf}^2 (largest squared row norm, FP32) are returned too
+ * (host outputs; tau and norm2inf optional).  Errors: NOT_PREPARED,
+ * INVALID_ARG (eps <= delta, delta < 0, eta outside (0, 1), or J K beyond
+ * the supported range).
+ */
+int kerdock_theory_params(kerdock_handle h, float eps, float delta, float eta, int32_t *J, int32_t *K,
+                          float *tau, float *norm2inf);
+
 /* kerdock_query -- geometry of a handle; `info` is host memory. */
 int kerdock_query(kerdock_handle h, kerdock_info *info);
 

@@ -20,7 +20,7 @@ std::vector<uint16_t> kerdock_masks(int k, uint32_t *poly_out);
 
 int launch_signs(const uint16_t *masks, int k, uint32_t *signs, hipStream_t s);
 int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dtype dt,
-                      float *scales, hipStream_t s);
+                      float *scales, float *norm2, hipStream_t s);
 int launch_table_build(kerdock_dtype dt, int k, const float *A, int m, int n, int pitch,
                        const uint32_t *signs, const float *scales, void *table, hipStream_t s);
 int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, int64_t L,
@@ -362,10 +362,20 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
         rc = hip_fail(e, "prepare copies");
     }
     if (rc == KERDOCK_OK) rc = launch_signs(h->masks, h->k, h->signs, s);
-    if (rc == KERDOCK_OK) rc = launch_row_scales(h->A, m, n, h->pitch, h->d, dtype, h->scales, s);
+    float *norm2 = nullptr;
+    if (rc == KERDOCK_OK && (e = hipMalloc((void **)&norm2, (size_t)h->pitch * 4)) != hipSuccess)
+        rc = fail(KERDOCK_ERR_OOM, "row norms");
+    if (rc == KERDOCK_OK) rc = launch_row_scales(h->A, m, n, h->pitch, h->d, dtype, h->scales, norm2, s);
     if (rc == KERDOCK_OK)
         rc = launch_table_build(dtype, h->k, h->A, m, n, h->pitch, h->signs, h->scales, h->table, s);
     if (rc == KERDOCK_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "prepare");
+    if (rc == KERDOCK_OK) {
+        std::vector<float> rn((size_t)m);
+        if ((e = hipMemcpy(rn.data(), norm2, (size_t)m * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+            rc = hip_fail(e, "row norms");
+        for (float v : rn) h->row_norm2_max = std::max(h->row_norm2_max, v);
+    }
+    (void)hipFree(norm2);
     if (rc != KERDOCK_OK) {
         free_handle(h);
         return rc;
@@ -387,6 +397,24 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
                          const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
                          int32_t *out_cnt, void *stream) {
     return kd::apply_internal(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, nullptr, stream);
+}
+
+int kerdock_theory_params(kerdock_handle h, float eps, float delta, float eta, int32_t *J, int32_t *K,
+                          float *tau, float *norm2inf) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    if (!(eps > delta) || !(delta >= 0.f) || !(eta > 0.f) || !(eta < 1.f) || !J || !K)
+        return fail(KERDOCK_ERR_INVALID_ARG, "need eps > delta >= 0, 0 < eta < 1 and outputs");
+    const double gamma = 0.5 * ((double)eps - (double)delta);
+    const double e = 2.718281828459045;
+    const double Jd = ceil(4.0 * e * e * (double)h->row_norm2_max / (gamma * gamma));
+    const double Kd = ceil(2.0 * log((double)h->m / (double)eta));
+    if (Jd > 2147483647.0 || Kd > 32.0 || Jd * Kd > 2147483583.0)
+        return fail(KERDOCK_ERR_INVALID_ARG, "Theorem 5's J or K exceeds the supported range (J K < 2^31, K <= 32)");
+    *J = (int32_t)(Jd < 1 ? 1 : Jd);
+    *K = (int32_t)(Kd < 1 ? 1 : Kd);
+    if (tau) *tau = 0.5f * (eps + delta);
+    if (norm2inf) *norm2inf = h->row_norm2_max;
+    return KERDOCK_OK;
 }
 
 int kerdock_query(kerdock_handle h, kerdock_info *info) {

@@ -46,23 +46,26 @@ __global__ void k_signs(const uint16_t *__restrict__ masks, int k, int words_per
 // |T[l]_i| (a Kerdock entry is a signed sum of a_i, an identity entry is
 // sqrt(d) a_i[w]), so a single pass can quantise.  Other dtypes: 1.
 __global__ void k_row_scales(const float *__restrict__ A, int m, int n, int pitch, float sqrt_d,
-                             int fp8, float *__restrict__ scales) {
+                             int fp8, float *__restrict__ scales, float *__restrict__ norm2) {
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (row >= pitch) return;
-    float l1 = 0.f, linf = 0.f;
+    float l1 = 0.f, linf = 0.f, l2 = 0.f;
     if (row < m) {
         for (int x = lane; x < n; x += 64) {
             float a = fabsf(A[(size_t)row * n + x]);
             l1 += a;
+            l2 += a * a;
             linf = fmaxf(linf, a);
         }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         l1 += __shfl_xor(l1, off);
+        l2 += __shfl_xor(l2, off);
         linf = fmaxf(linf, __shfl_xor(linf, off));
     }
+    if (lane == 0 && norm2) norm2[row] = row < m ? l2 : 0.f;
     if (lane == 0) {
         float s = 1.0f;
         if (fp8 && row < m) {
@@ -299,9 +302,9 @@ int launch_signs(const uint16_t *masks, int k, uint32_t *signs, hipStream_t s) {
 }
 
 int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dtype dt,
-                      float *scales, hipStream_t s) {
+                      float *scales, float *norm2, hipStream_t s) {
     hipLaunchKernelGGL(k_row_scales, dim3((pitch + 3) / 4), dim3(256), 0, s, A, m, n, pitch,
-                       sqrtf((float)d), dt == KERDOCK_FP8E4M3 ? 1 : 0, scales);
+                       sqrtf((float)d), dt == KERDOCK_FP8E4M3 ? 1 : 0, scales, norm2);
     KD_LAUNCH("k_row_scales");
     return KERDOCK_OK;
 }

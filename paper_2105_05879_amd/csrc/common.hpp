@@ -120,4 +120,5 @@ struct kerdock_handle_s {
     int tune_chunk = 0;           // draws per gather workgroup (0: default)
     int tune_unroll = 0;          // draws in flight per thread (0: default)
     kerdock_learned_s *learned = nullptr;   // attached learned-proposal state
+    float row_norm2_max = 0.f;    // |A|_{2->inf}^2: largest squared row norm
 };

@@ -74,6 +74,9 @@ EXPORTS = {
     "kerdock_learned_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                                              ctypes.c_int, ctypes.POINTER(ApplyParams), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_theory_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "kerdock_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]),
@@ -428,3 +431,11 @@ def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None,
     _check(lib().kerdock_learned_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max, ctypes.byref(p),
                                        _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(fb), _stream(stream)))
     return out[0], out[1], out[2], fb
+
+
+def kerdock_theory_params(h, eps, delta, eta):
+    """Theorem 5's (J, K), tau = (eps + delta)/2 and |A|_{2->inf}^2."""
+    J, K, tau, nrm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float(), ctypes.c_float()
+    _check(lib().kerdock_theory_params(h.ptr, float(eps), float(delta), float(eta), ctypes.byref(J),
+                                       ctypes.byref(K), ctypes.byref(tau), ctypes.byref(nrm)))
+    return J.value, K.value, tau.value, nrm.value

@@ -186,3 +186,27 @@ def paper_regime(batch=16, n=4096, s=20, seed_A=SEED_A + 6, seed_X=SEED_X + 6):
         sup.append(su)
     X = Y @ A                                 # rows: (A^T y)^T, already unit
     return Workload("paper", A, X, 0.5 / np.sqrt(s), sup, s)
+
+
+def near_sparse(batch=400, m=768, n=1000, s=8, delta=0.02, seed_A=SEED_A + 7, seed_X=SEED_X + 7):
+    """x in Sigma(A, s, delta) for a wide A (m < n) with orthonormal rows (the
+    first m rows of a Haar orthogonal n x n matrix, so |A|_{2->inf} = 1):
+    y = Ax has every entry uniform in [-delta, delta] except s entries of
+    equal magnitude and random sign on a random support, that magnitude
+    chosen so that |y| = 1, and x = A^T y is then a unit vector.  eps is set
+    at 0.85 of the smallest magnitude that planting can give."""
+    A = haar_orthogonal(n, np.random.default_rng(seed_A))[:m]
+    rx = np.random.default_rng(seed_X)
+    Y = rx.uniform(-delta, delta, size=(batch, m))
+    sup = []
+    for r in range(batch):
+        su = np.sort(rx.choice(m, size=s, replace=False))
+        Y[r, su] = 0.0
+        mag = np.sqrt((1.0 - np.dot(Y[r], Y[r])) / s)
+        Y[r, su] = rx.choice([-1.0, 1.0], size=s) * mag
+        sup.append(su)
+    X = Y @ A
+    mag_min = np.sqrt((1.0 - m * delta * delta) / s)
+    w = Workload("near_sparse", A, X, 0.85 * mag_min, sup, s)
+    w.delta = float(delta)
+    return w
