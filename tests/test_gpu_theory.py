@@ -1,0 +1,72 @@
+"""Theorem 5's parameters on the GPU path, with delta > 0 and a rectangular
+A: the entry point's (J, K, tau) against the theorem's formulas, and the
+whole streaming step keeping exactly supp(h_eps(Ax)) with its values for at
+least a 1 - eta fraction of a batch drawn from Sigma(A, s, delta)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import need_gpu
+from paper_2105_05879_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def near():
+    return workloads.near_sparse(batch=400)
+
+
+def theorem5(A, eps, delta, eta):
+    gamma = 0.5 * (eps - delta)
+    norm2 = float(np.max(np.sum(np.asarray(A, dtype=np.float64) ** 2, axis=1)))
+    return (4 * math.e ** 2 * norm2 / gamma ** 2, 2 * math.log(A.shape[0] / eta), norm2)
+
+
+def test_theory_params_match_theorem5(near):
+    kd = need_gpu()
+    w = near
+    h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), "f32")
+    for eta in (0.5, 0.05, 1e-4):
+        J, K, tau, nrm = kd.kerdock_theory_params(h, w.eps, w.delta, eta)
+        Jw, Kw, nw = theorem5(w.A, w.eps, w.delta, eta)
+        assert abs(nrm - nw) <= 1e-5 * nw
+        # FP32 row norms may move a J that sits next to an integer by one
+        assert J == math.ceil(Jw) or (abs(J - Jw) < 1 and abs(Jw - round(Jw)) < 1e-3 * Jw)
+        assert K == math.ceil(Kw)
+        assert tau == pytest.approx(0.5 * (w.eps + w.delta), rel=1e-7)
+    with pytest.raises(kd.KerdockError):
+        kd.kerdock_theory_params(h, w.delta, w.delta, 0.05)
+    with pytest.raises(kd.KerdockError):
+        kd.kerdock_theory_params(h, w.eps, -0.1, 0.05)
+    with pytest.raises(kd.KerdockError):
+        kd.kerdock_theory_params(h, w.eps, w.delta, 1.0)
+    with pytest.raises(kd.KerdockError):
+        kd.kerdock_theory_params(h, 1e-4, 0.0, 1e-30)      # K > 32
+    h.destroy()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_failure_rate_at_most_eta(near, dtype):
+    kd = need_gpu()
+    w = near
+    eta = 0.05
+    h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
+    J, K, tau, _ = kd.kerdock_theory_params(h, w.eps, w.delta, eta)
+    X = torch.from_numpy(w.X).cuda()
+    idx, val, cnt = kd.kerdock_sparse_apply(h, X, w.eps, w.s, J, K, seed=5, tau=tau)
+    torch.cuda.synchronize()
+    idx, val, cnt = idx.cpu().numpy(), val.cpu().numpy(), cnt.cpu().numpy()
+    Y = w.X.astype(np.float64) @ w.A.astype(np.float64).T
+    fails = 0
+    for t in range(w.batch):
+        sup = w.supports[t]
+        ok = cnt[t] == len(sup) and np.array_equal(idx[t][:cnt[t]], sup)
+        if ok:
+            assert np.allclose(val[t][:cnt[t]], Y[t][sup], rtol=1e-5, atol=1e-6)
+        fails += not ok
+    print("J=%d K=%d tau=%.4f failures %d of %d" % (J, K, tau, fails, w.batch))
+    assert fails <= eta * w.batch
+    h.destroy()
