@@ -239,6 +239,86 @@ def batched_form(kd, torch, np, workloads, args):
     return res
 
 
+def paper_form(kd, torch, np, workloads, args):
+    """The numerical section's regime: n = 4096, A random orthogonal, Ax with
+    exactly 20 nonzero entries of equal magnitude, J = 375, K = 2, S = the 200
+    largest estimates, eps half the planted magnitude.  Each table type runs
+    a 4096-vector batch per call (throughput) and one vector per call (the
+    paper's one-x-at-a-time setting), against FP32 GEMV (one x per call) and
+    GEMM (the whole batch) on the same GPU; exact recovery counts vectors whose
+    output is exactly the planted support with its values."""
+    B = 4096
+    w = workloads.paper_regime(batch=B)
+    A = torch.from_numpy(w.A).cuda()
+    X = torch.from_numpy(w.X).cuda()
+    Y = w.X.astype(np.float64) @ w.A.astype(np.float64).T
+    J, K, S = 375, 2, 200
+    res = {"workload": "n=4096 Haar A, %d x with 20-sparse Ax (equal magnitudes), J=375 K=2 "
+                       "s_max=200, eps=%.4f" % (B, w.eps)}
+    for dt in ("f32", "bf16"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = kd.kerdock_prepare(A, dt)
+        torch.cuda.synchronize()
+        prep = time.perf_counter() - t0
+        kd.kerdock_reserve(h, B, J, K, S)
+        out = (torch.empty((B, S), dtype=torch.int32, device="cuda"),
+               torch.empty((B, S), dtype=torch.float32, device="cuda"),
+               torch.empty((B,), dtype=torch.int32, device="cuda"))
+        one = tuple(o[:1] for o in out)
+        ms = (ctypes.c_float * 4)()
+        for sidx in range(args.warmup):
+            kd.kerdock_sparse_apply(h, X, w.eps, S, J, K, 2021, t0=sidx * B, out=out)
+        torch.cuda.synchronize()
+        kern = np.zeros(4)
+        t0 = time.perf_counter()
+        for sidx in range(args.steps):
+            kd.kerdock_sparse_apply(h, X, w.eps, S, J, K, 2021, t0=sidx * B, out=out, kernel_ms=ms)
+            kern += np.array(ms[:4])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern /= args.steps
+        idx, val, cnt = (o.cpu().numpy() for o in out)
+        exact = 0
+        for t in range(B):
+            sup = w.supports[t]
+            if cnt[t] == len(sup) and np.array_equal(idx[t][:cnt[t]], sup) and np.allclose(
+                    val[t][:cnt[t]], Y[t][sup], rtol=1e-5, atol=1e-7):
+                exact += 1
+        reps = 2000
+        for t in range(20):
+            kd.kerdock_sparse_apply(h, X[t:t + 1], w.eps, S, J, K, 2021, t0=t, out=one)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for t in range(reps):
+            kd.kerdock_sparse_apply(h, X[t % B:t % B + 1], w.eps, S, J, K, 2021, t0=t, out=one)
+        torch.cuda.synchronize()
+        single = reps / (time.perf_counter() - t1)
+        col_bytes = h.info.m * BYTES[dt]
+        gbps = B * J * K * col_bytes / (kern[1] * 1e-3) / 1e9
+        res[dt] = {"x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                   "x_per_s_one_per_call": single, "exact_recovery": exact / B, "prepare_s": prep,
+                   "table_GB": h.info.table_bytes / 1e9,
+                   "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2],
+                                 "survivors": kern[3]},
+                   "gather_GBps": gbps}
+        log("paper regime %s: prepare %.1f s, %.0f x/s batched (gather %.3f ms %.0f GB/s, select "
+            "%.3f, survivors %.3f), %.0f x/s one per call, exact %d/%d"
+            % (dt, prep, res[dt]["x_per_s"], kern[1], gbps, kern[2], kern[3], single, exact, B))
+        h.destroy()
+        torch.cuda.empty_cache()
+    base = dense_baselines(torch, A, X)
+    res["dense_gemv_f32_x_per_s"] = base["dense_gemv_f32_x_per_s"]
+    res["dense_gemm_f32_x_per_s"] = base["dense_gemm_f32_x_per_s"]
+    res["one_per_call_vs_gemv"] = res["f32"]["x_per_s_one_per_call"] / base["dense_gemv_f32_x_per_s"]
+    res["batched_vs_gemm"] = res["f32"]["x_per_s"] / base["dense_gemm_f32_x_per_s"]
+    log("paper regime dense: GEMV %.0f x/s, GEMM %.0f x/s" % (base["dense_gemv_f32_x_per_s"],
+                                                              base["dense_gemm_f32_x_per_s"]))
+    del A, X
+    torch.cuda.empty_cache()
+    return res
+
+
 def learned_form(kd, torch, np, workloads, args):
     """n = 1024 structured dictionary, supports from a pool of 512 size-16
     patterns: the MLP proposer (1024 -> 512 -> 512 -> 1024) is trained on
@@ -416,6 +496,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
+    ap.add_argument("--no-paper", action="store_true", help="skip the numerical-section regime")
     ap.add_argument("--learned-train", type=int, default=1 << 18)
     ap.add_argument("--learned-test", type=int, default=1 << 14)
     ap.add_argument("--learned-epochs", type=int, default=8)
@@ -469,6 +550,8 @@ def main():
         forms["batched"] = batched_form(kd, torch, np, workloads, args)
     if not args.no_learned:
         forms["learned"] = learned_form(kd, torch, np, workloads, args)
+    if not args.no_paper:
+        forms["paper_regime"] = paper_form(kd, torch, np, workloads, args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A64, X64, head["J"], head["K"], args.eps, args.s_max, args.seed)

@@ -45,18 +45,23 @@ int hip_fail(hipError_t e, const char *what) {
     return e == hipErrorOutOfMemory ? KERDOCK_ERR_OOM : KERDOCK_ERR_HIP;
 }
 
-// Streaming-step tuning: draws per gather chunk and loads in flight per
-// thread.  Overridable with KERDOCK_CHUNK / KERDOCK_UNROLL.
+// Streaming-step tuning: loads in flight per thread (results do not depend
+// on it); overridable with KERDOCK_UNROLL.
 static int env_int(const char *name, int dflt) {
     const char *v = getenv(name);
     if (!v || !*v) return dflt;
     return atoi(v);
 }
 
-static int gather_chunk(const kerdock_handle_s *h, int J) {
-    int c = env_int("KERDOCK_CHUNK", h->tune_chunk > 0 ? h->tune_chunk : 512);
-    if (c < 16) c = 16;
-    if (c > gather_chunk_max()) c = gather_chunk_max();
+// Draws per FP32 partial sum: the caller's value, else the tuned one, else
+// about J/8 (so that a single vector still spreads over several chunks per
+// batch) between 16 and 512; never above J.
+int chunk_for(const kerdock_handle_s *h, int J, int requested) {
+    int c;
+    if (requested > 0) c = requested;
+    else if (h->tune_chunk > 0) c = h->tune_chunk;
+    else c = std::min(512, std::max(16, (J + 7) / 8));
+    c = std::min(c, gather_chunk_max());
     return c < J ? c : J;
 }
 
@@ -66,21 +71,19 @@ static int gather_unroll(const kerdock_handle_s *h) {
 
 // workspace layout of the streaming step
 struct Workspace {
-    size_t partial, surv, nsurv, total;
+    size_t partial, surv, nsurv, svals, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max) {
-    const size_t N = (size_t)J * K;
-    const int chunk = gather_chunk(h, J);
+static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max, int chunk) {
     const size_t cpb = (J + chunk - 1) / chunk;
     Workspace w;
     size_t off = 0;
-    (void)N;
     w.partial = off; off += align256((size_t)batch * K * cpb * h->pitch * 4);
     w.surv = off;    off += align256((size_t)batch * s_max * 4);
     w.nsurv = off;   off += align256((size_t)batch * 4);
+    w.svals = off;   off += align256((size_t)batch * s_max * 4);
     w.total = off;
     return w;
 }
@@ -154,21 +157,24 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     if (p->J < 1 || p->K < 1 || p->K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "need J >= 1, 1 <= K <= 32");
     if ((int64_t)p->J * p->K > ((int64_t)1 << 31) - 64)
         return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
+    if (p->chunk < 0 || p->chunk > gather_chunk_max())
+        return fail(KERDOCK_ERR_INVALID_ARG, "chunk must lie in [0, 1024]");
     if (batch == 0) return KERDOCK_OK;
     if (!X || !out_idx || !out_val || !out_cnt)
         return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int J = p->J, K = p->K, N = J * K;
+    const int chunk = chunk_for(h, J, p->chunk);
+    const int cpb = (J + chunk - 1) / chunk;
 
-    const Workspace lay = workspace_layout(h, batch, J, K, s_max);
+    const Workspace lay = workspace_layout(h, batch, J, K, s_max, chunk);
     int rc = ensure_workspace(h, lay.total);
     if (rc != KERDOCK_OK) return rc;
     char *ws = reinterpret_cast<char *>(h->ws);
     float *partial = reinterpret_cast<float *>(ws + lay.partial);
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
-    const int chunk = gather_chunk(h, J);
-    const int cpb = (J + chunk - 1) / chunk;
+    float *svals = reinterpret_cast<float *>(ws + lay.svals);
     if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
         return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
 
@@ -208,7 +214,8 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, active};
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
-    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr};
+    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr,
+                svals, surv_vec4(X, h->n)};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;
@@ -390,7 +397,7 @@ int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max) {
     if (batch < 0 || J < 1 || K < 1 || K > 32 || s_max < 1 || s_max > h->m)
         return fail(KERDOCK_ERR_INVALID_ARG, "reserve: invalid sizes");
     KD_HIP(hipSetDevice(h->device));
-    return ensure_workspace(h, workspace_layout(h, batch, J, K, s_max).total);
+    return ensure_workspace(h, workspace_layout(h, batch, J, K, s_max, chunk_for(h, J, 0)).total);
 }
 
 int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps, int s_max,

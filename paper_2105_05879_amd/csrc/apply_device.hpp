@@ -187,8 +187,12 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
             for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
         const float sqrt_d = sqrtf((float)d);
 
-        for (int r0 = wave * 64; r0 < cnt; r0 += 4 * 64) {
-            const int jn = min(64, cnt - r0);
+        // the four waves take equal runs of the chunk's draws (a multiple of
+        // four each), 64 at a time, one draw per lane for the Philox block
+        const int per = ((cnt + 3) / 4 + 3) & ~3;
+        const int rend = min(cnt, (wave + 1) * per);
+        for (int r0 = wave * per; r0 < rend; r0 += 64) {
+            const int jn = min(64, rend - r0);
             uint32_t my_l = 0;
             if (lane < jn) {
                 const int j = jbeg + r0 + lane;
@@ -486,9 +490,19 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
         for (int a = 0; a < KMAX; ++a) {
             float s = INFINITY;
             if (a < K) {
+                // partials of batch a summed in chunk order; eight loads in
+                // flight at a time
+                const float *pa = pt + (size_t)a * chunks_per_batch * pitch + i;
                 s = 0.f;
-                for (int c = 0; c < chunks_per_batch; ++c)
-                    s += pt[(size_t)(a * chunks_per_batch + c) * pitch + i];
+                int c = 0;
+                for (; c + 8 <= chunks_per_batch; c += 8) {
+                    float q[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) q[u] = pa[(size_t)(c + u) * pitch];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s += q[u];
+                }
+                for (; c < chunks_per_batch; ++c) s += pa[(size_t)c * pitch];
                 s = s / (float)J;
             }
             v[a] = s;
@@ -549,70 +563,87 @@ struct SurvArgs {
     float *dbg_values;        // optional [batch][s_max]
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
     float *vsum2;             // optional [batch]: sum over S of (a_i.x)^2
+    float *svals;             // [batch][s_max] survivor values (split launch)
+    int vec4;                 // rows of A and X may be read as 16-byte pieces
 };
 
-constexpr int SURV_THREADS = 256;
+// 16-byte pieces are legal when n is a multiple of 4 and X is 16-byte
+// aligned (A is a device allocation of m x n floats).
+inline int surv_vec4(const float *X, int n) {
+    return (n % 4 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+}
 
-// shared memory: vals[s_max]
-__device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *vals) {
+constexpr int SURV_THREADS = 256;
+constexpr int SURV_SPLIT_BATCH = 2048;   // below this many vectors use the split form
+
+// a_i.x by one wave: compensated FP32 dot product (Ogita-Rump-Oishi Dot2).
+// Lane l takes elements l, l + 64, ... (or the 16-byte pieces l, l + 64,
+// ... in element order within each piece), then a compensated butterfly.
+__device__ __forceinline__ float survivor_dot(const float *__restrict__ row, const float *__restrict__ x,
+                                              int n, int vec4) {
 #pragma clang fp contract(off)
-    const float *__restrict__ A = a.A;
-    const int n = a.n, s_max = a.s_max;
-    const float *__restrict__ X = a.X;
-    const int32_t *__restrict__ surv = a.surv;
-    const int32_t *__restrict__ nsurv = a.nsurv;
-    const float eps = a.eps;
-    int32_t *__restrict__ out_idx = a.out_idx;
-    float *__restrict__ out_val = a.out_val;
-    int32_t *__restrict__ out_cnt = a.out_cnt;
-    float *__restrict__ dbg_values = a.dbg_values;
-    if (a.active && !a.active[t]) return;      // uniform over the workgroup
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int ns = min(nsurv[t], s_max);
-    const float *x = X + (size_t)t * n;
-    for (int s = wave; s < ns; s += SURV_THREADS / 64) {
-        const int i = surv[(size_t)t * s_max + s];
-        const float *row = A + (size_t)i * n;
-        float p = 0.f, e = 0.f;
-        for (int q = lane; q < n; q += 64) {
-            const float a = row[q], b = x[q];
-            const float h = a * b;
-            const float rr = fmaf(a, b, -h);
-            float sum, err;
-            two_sum(p, h, sum, err);
-            p = sum;
-            e = e + (err + rr);
+    const int lane = threadIdx.x & 63;
+    float p = 0.f, e = 0.f;
+    auto step = [&](float a, float b) {
+        const float h = a * b;
+        const float rr = fmaf(a, b, -h);
+        float sum, err;
+        two_sum(p, h, sum, err);
+        p = sum;
+        e = e + (err + rr);
+    };
+    if (vec4) {
+        const float4 *__restrict__ r4 = reinterpret_cast<const float4 *>(row);
+        const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
+        const int n4 = n >> 2;
+#pragma unroll 4
+        for (int q = lane; q < n4; q += 64) {
+            const float4 a = r4[q], b = x4[q];
+            step(a.x, b.x);
+            step(a.y, b.y);
+            step(a.z, b.z);
+            step(a.w, b.w);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const float p2 = __shfl_xor(p, off), e2 = __shfl_xor(e, off);
-            float sum, err;
-            two_sum(p, p2, sum, err);
-            p = sum;
-            e = e + e2 + err;
-        }
-        if (lane == 0) vals[s] = p + e;
+    } else {
+        for (int q = lane; q < n; q += 64) step(row[q], x[q]);
     }
-    __syncthreads();
-    if (wave != 0) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float p2 = __shfl_xor(p, off), e2 = __shfl_xor(e, off);
+        float sum, err;
+        two_sum(p, p2, sum, err);
+        p = sum;
+        e = e + e2 + err;
+    }
+    return p + e;
+}
+
+// Threshold and compaction of the values of vector t by one wave: rows of S
+// with |a_i.x| >= eps, in ascending row order, then padding; optional debug
+// values and sum of squares.
+__device__ __forceinline__ void survivors_compact(const SurvArgs &a, int t, const float *vals) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    const int s_max = a.s_max;
+    const int ns = min(a.nsurv[t], s_max);
     int base = 0;
     for (int s0 = 0; s0 < s_max; s0 += 64) {
         const int s = s0 + lane;
-        const bool keep = s < ns && fabsf(vals[s]) >= eps;
+        const bool keep = s < ns && fabsf(vals[s]) >= a.eps;
         const uint64_t mask = __ballot(keep);
         const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
         if (keep) {
-            out_idx[(size_t)t * s_max + pos] = surv[(size_t)t * s_max + s];
-            out_val[(size_t)t * s_max + pos] = vals[s];
+            a.out_idx[(size_t)t * s_max + pos] = a.surv[(size_t)t * s_max + s];
+            a.out_val[(size_t)t * s_max + pos] = vals[s];
         }
         base += __popcll(mask);
     }
     for (int s = base + lane; s < s_max; s += 64) {
-        out_idx[(size_t)t * s_max + s] = -1;
-        out_val[(size_t)t * s_max + s] = 0.f;
+        a.out_idx[(size_t)t * s_max + s] = -1;
+        a.out_val[(size_t)t * s_max + s] = 0.f;
     }
-    if (dbg_values)
-        for (int s = lane; s < s_max; s += 64) dbg_values[(size_t)t * s_max + s] = s < ns ? vals[s] : 0.f;
+    if (a.dbg_values)
+        for (int s = lane; s < s_max; s += 64) a.dbg_values[(size_t)t * s_max + s] = s < ns ? vals[s] : 0.f;
     if (a.vsum2) {
         float e2 = 0.f;
         for (int s = lane; s < ns; s += 64) e2 += vals[s] * vals[s];
@@ -620,7 +651,32 @@ __device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *v
         for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
         if (lane == 0) a.vsum2[t] = e2;
     }
-    if (lane == 0) out_cnt[t] = base;
+    if (lane == 0) a.out_cnt[t] = base;
+}
+
+// Whole survivor step of vector t in one workgroup (shared memory:
+// vals[s_max]): waves take rows of S in turn, then wave 0 compacts.
+__device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *vals) {
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ns = min(a.nsurv[t], a.s_max);
+    const float *x = a.X + (size_t)t * a.n;
+    for (int s = wave; s < ns; s += SURV_THREADS / 64) {
+        const float v = survivor_dot(a.A + (size_t)a.surv[(size_t)t * a.s_max + s] * a.n, x, a.n, a.vec4);
+        if (lane == 0) vals[s] = v;
+    }
+    __syncthreads();
+    if (wave == 0) survivors_compact(a, t, vals);
+}
+
+// Split form, for small batches: one wave per row of S across many
+// workgroups (values to a.svals), then one wave per vector compacts.
+__device__ __forceinline__ void survivor_dots_split(const SurvArgs &a, int t, int s) {
+    if (a.active && !a.active[t]) return;
+    if (s >= min(a.nsurv[t], a.s_max)) return;
+    const float v = survivor_dot(a.A + (size_t)a.surv[(size_t)t * a.s_max + s] * a.n,
+                                 a.X + (size_t)t * a.n, a.n, a.vec4);
+    if ((threadIdx.x & 63) == 0) a.svals[(size_t)t * a.s_max + s] = v;
 }
 
 }  // namespace kd

@@ -28,6 +28,18 @@ __global__ __launch_bounds__(SURV_THREADS) void k_survivors(SurvArgs a) {
     survivors_vec(a, blockIdx.x, vals);
 }
 
+// split survivor step: grid (ceil(s_max / 4), batch), one row of S per wave
+__global__ __launch_bounds__(SURV_THREADS) void k_survivor_dots(SurvArgs a) {
+    survivor_dots_split(a, blockIdx.y, blockIdx.x * (SURV_THREADS / 64) + (threadIdx.x >> 6));
+}
+
+// grid (batch), one wave
+__global__ __launch_bounds__(64) void k_survivor_compact(SurvArgs a) {
+    const int t = blockIdx.x;
+    if (a.active && !a.active[t]) return;
+    survivors_compact(a, t, a.svals + (size_t)t * a.s_max);
+}
+
 // Learned form: the c rows of largest logit (ties: smaller index), ascending.
 // Keys map floats monotonically to unsigned integers.
 __global__ __launch_bounds__(SELECT_THREADS) void k_topc_logits(const float *__restrict__ Z, int m, int c,
@@ -71,12 +83,19 @@ int launch_fallback_flags(const float *E, const float *vsum2, int B, float tol, 
 }
 
 
-GatherShape gather_shape(kerdock_dtype dt, int pitch) {
+GatherShape gather_shape(kerdock_dtype dt, int pitch, long long work) {
     GatherShape g;
+    g.small = 0;
     g.col_bytes = pitch * (int)dtype_bytes(dt);
     if (g.col_bytes >= TILE_BYTES) {
         const int need = (g.col_bytes + TILE_BYTES - 1) / TILE_BYTES;
         g.tiles = need >= 3 ? 4 : need;
+        // few chunks in the launch: one 4 KiB tile per workgroup, for more
+        // workgroups (each entry still sums its draws in the same order)
+        if (work * ((need + g.tiles - 1) / g.tiles) < GATHER_MIN_WGS) {
+            g.tiles = 1;
+            g.small = 1;
+        }
         g.segs = (g.col_bytes + g.tiles * TILE_BYTES - 1) / (g.tiles * TILE_BYTES);
         g.groups = 1;
         g.tpc = GATHER_THREADS;
@@ -121,7 +140,9 @@ static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const DGArgs 
 
 int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int unroll, hipStream_t s) {
     if (a.chunk < 1 || a.chunk > MAX_CHUNK) return fail(KERDOCK_ERR_INVALID_ARG, "gather chunk out of range");
-    const GatherShape g = gather_shape(dt, a.pitch);
+    const GatherShape g = gather_shape(dt, a.pitch, (long long)batch * K * a.chunks_per_batch);
+    // a launch too small to fill the chip is latency-bound: most loads in flight
+    if (g.small) unroll = 16;
     dim3 grid(K * a.chunks_per_batch, g.segs, batch);
     switch (dt) {
     case KERDOCK_F32: launch_dt<KERDOCK_F32>(grid, g, unroll, a, s); break;
@@ -146,6 +167,17 @@ int launch_select(const SelArgs &a, int batch, hipStream_t s) {
 }
 
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s) {
+    // One workgroup per vector fills the chip when there are many vectors;
+    // otherwise spread the rows of S over one wave each.
+    if (a.svals && batch < SURV_SPLIT_BATCH) {
+        if (batch > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "batch too large for the split survivor grid");
+        const int per = SURV_THREADS / 64;
+        hipLaunchKernelGGL(k_survivor_dots, dim3((a.s_max + per - 1) / per, batch), dim3(SURV_THREADS), 0, s, a);
+        KD_LAUNCH("k_survivor_dots");
+        hipLaunchKernelGGL(k_survivor_compact, dim3(batch), dim3(64), 0, s, a);
+        KD_LAUNCH("k_survivor_compact");
+        return KERDOCK_OK;
+    }
     hipLaunchKernelGGL(k_survivors, dim3(batch), dim3(SURV_THREADS), (size_t)a.s_max * sizeof(float), s, a);
     KD_LAUNCH("k_survivors");
     return KERDOCK_OK;

@@ -90,8 +90,14 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t byte) {
 // workgroup, segments per column, and the draw groups of short columns
 struct GatherShape {
     int col_bytes, tiles, segs, groups, tpc, grouped;
+    int small;    // launch below GATHER_MIN_WGS workgroups: single tiles
 };
-GatherShape gather_shape(kerdock_dtype dt, int pitch);
+// work: chunks of draws in the launch (vectors x batches x chunks); below
+// GATHER_MIN_WGS workgroups the columns are split into single tiles
+constexpr long long GATHER_MIN_WGS = 2048;
+GatherShape gather_shape(kerdock_dtype dt, int pitch, long long work = 1ll << 40);
+// draws per FP32 partial sum for a call with J draws per batch
+int chunk_for(const kerdock_handle_s *h, int J, int requested);
 
 }  // namespace kd
 

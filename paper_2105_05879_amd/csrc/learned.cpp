@@ -357,7 +357,8 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
     rc = launch_features(h->k, X, B, h->n, nullptr, n->F16, s);
     if (rc == KERDOCK_OK) rc = mlp_forward16(n, B, nullptr, s);
     if (rc == KERDOCK_OK) rc = launch_topc_logits(n->Z, B, h->m, s_max, cand, ncand, s);
-    SurvArgs va{h->A, h->n, X, cand, ncand, s_max, eps, out_idx, out_val, out_cnt, nullptr, nullptr, vs2};
+    SurvArgs va{h->A, h->n, X, cand, ncand, s_max, eps, out_idx, out_val, out_cnt, nullptr, nullptr, vs2,
+                nullptr, surv_vec4(X, h->n)};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, B, s);
     // L5 energy check: |Ax|^2 = x^T G x against the verified energy
     if (rc == KERDOCK_OK)

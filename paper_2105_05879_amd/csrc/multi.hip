@@ -288,9 +288,11 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
     for (int q = 0; q < nh; ++q) {
         const kerdock_handle h = hs[q];
         const int J = params[q].J, K = params[q].K;
-        int c = h->tune_chunk > 0 ? h->tune_chunk : 512;
-        c = std::min(c, gather_chunk_max());
-        chunk[q] = std::min(c, J);
+        if (params[q].chunk < 0 || params[q].chunk > gather_chunk_max()) {
+            delete pl;
+            return fail(KERDOCK_ERR_INVALID_ARG, "multi: chunk must lie in [0, 1024]");
+        }
+        chunk[q] = chunk_for(h, J, params[q].chunk);
         cpb[q] = (J + chunk[q] - 1) / chunk[q];
         nchunks[q] = K * cpb[q];
         const GatherShape gs = gather_shape(h->dtype, h->pitch);
@@ -359,7 +361,8 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         int32_t *ns_ = reinterpret_cast<int32_t *>(ws + off_nsurv[q]);
         sel[q] = SelArgs{a.partial, h->m, h->pitch, p->K, cpb[q], p->J, h->scales, s_max[q], p->tau,
                          nullptr, sv_, ns_};
-        sv[q] = SurvArgs{h->A, h->n, X[q], sv_, ns_, s_max[q], eps, out_idx[q], out_val[q], out_cnt[q], nullptr};
+        sv[q] = SurvArgs{h->A, h->n, X[q], sv_, ns_, s_max[q], eps, out_idx[q], out_val[q], out_cnt[q], nullptr,
+                         nullptr, nullptr, nullptr, surv_vec4(X[q], h->n)};
         t0[q] = p->t0;
     }
     // work items, longest columns first

@@ -32,7 +32,8 @@ class ApplyParams(ctypes.Structure):
                 ("t0", ctypes.c_int64), ("tau", ctypes.c_float),
                 ("dbg_samples", ctypes.c_void_p), ("dbg_coef", ctypes.c_void_p),
                 ("dbg_mu", ctypes.c_void_p), ("dbg_survivors", ctypes.c_void_p),
-                ("dbg_values", ctypes.c_void_p), ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
+                ("dbg_values", ctypes.c_void_p), ("kernel_ms", ctypes.POINTER(ctypes.c_float)),
+                ("chunk", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -192,7 +193,7 @@ def kerdock_reserve(h, batch, J, K, s_max):
 
 
 def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
-                         stream=None, kernel_ms=None):
+                         stream=None, kernel_ms=None, chunk=0):
     """h_eps(Ax) on the s_max rows of largest median-of-means estimate.
 
     Returns (idx [B, s_max] int32, val [B, s_max] f32, cnt [B] int32) and,
@@ -206,7 +207,7 @@ def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, 
                torch.empty((B, s_max), dtype=torch.float32, device=dev),
                torch.empty((B,), dtype=torch.int32, device=dev))
     idx, val, cnt = out
-    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau)
+    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau, chunk=chunk)
     if kernel_ms is not None:          # a ctypes c_float * 4 filled by the call
         p.kernel_ms = ctypes.cast(kernel_ms, ctypes.POINTER(ctypes.c_float))
     dbg = None
@@ -297,7 +298,7 @@ def _multi_args(handles, Xs, params, s_max, outs):
     ps = (ApplyParams * nh)()
     for q, p in enumerate(params):
         ps[q] = ApplyParams(J=p["J"], K=p["K"], seed=p.get("seed", 0), t0=p.get("t0", 0),
-                            tau=p.get("tau", 0.0))
+                            tau=p.get("tau", 0.0), chunk=p.get("chunk", 0))
     hs = _arr(ctypes.c_void_p, [h.ptr.value if isinstance(h.ptr, ctypes.c_void_p) else h.ptr for h in handles])
     xp = _arr(ctypes.c_void_p, [_dev(X, torch.float32, "X").value for X in Xs])
     bt = _arr(ctypes.c_int, [X.shape[0] for X in Xs])
@@ -418,7 +419,7 @@ def kerdock_learned_attach(h, net):
     h._net = net                      # keep the network alive with the handle
 
 
-def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, stream=None):
+def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, stream=None, chunk=0):
     """Returns (idx, val, cnt, fallback)."""
     B = X.shape[0]
     dev = X.device
@@ -427,7 +428,7 @@ def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None,
                torch.empty((B, s_max), dtype=torch.float32, device=dev),
                torch.empty((B,), dtype=torch.int32, device=dev))
     fb = torch.empty((B,), dtype=torch.int32, device=dev)
-    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau)
+    p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau, chunk=chunk)
     _check(lib().kerdock_learned_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max, ctypes.byref(p),
                                        _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(fb), _stream(stream)))
     return out[0], out[1], out[2], fb

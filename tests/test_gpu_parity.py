@@ -113,7 +113,7 @@ APPLY_CASES = [
 ]
 
 
-def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, eps=None):
+def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, eps=None, chunk=0):
     if m == n and n >= 64:
         A = workloads.structured_dictionary(n, np.random.default_rng(n)).astype(np.float32)
     else:
@@ -125,7 +125,7 @@ def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, e
         eps = float(np.quantile(np.abs(X64 @ A64.T), 0.9)) + 1e-6
     h = prepare(kd, A, dtype)
     idx, val, cnt, dbg = kd.kerdock_sparse_apply(h, torch.from_numpy(X).cuda(), eps, s_max, J, K,
-                                                  seed, t0=t0, tau=tau, debug=True)
+                                                  seed, t0=t0, tau=tau, debug=True, chunk=chunk)
     torch.cuda.synchronize()
     g = {key: v.cpu().numpy() for key, v in dbg.items()}
     g.update(idx=idx.cpu().numpy(), val=val.cpu().numpy(), cnt=cnt.cpu().numpy())
@@ -207,6 +207,36 @@ def test_median_all_batch_counts(orc, K):
     check_case(orc, A64, X64, g, r, info, eps, 7, K, 12, "f32")
 
 
+@pytest.mark.parametrize("chunk", [1, 3, 47, 1024])
+def test_chunk_parameter(orc, chunk):
+    """An explicit number of draws per FP32 partial sum, from one draw per
+    partial to more than J."""
+    kd = need_gpu()
+    A64, X64, g, r, info, eps = run_case(orc, kd, 100, 100, 300, 3, 20, "f32", chunk=chunk)
+    check_case(orc, A64, X64, g, r, info, eps, 300, 3, 20, "f32", chunk=chunk)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_results_do_not_depend_on_batch_size(orc, dtype):
+    """Launch shapes change with the batch (single-tile gather workgroups and
+    the split survivor step below 2048 vectors); the outputs of a vector
+    depend only on its stream position."""
+    kd = need_gpu()
+    n = 1200                                   # 4800-byte FP32 columns: two tiles
+    A = rand_A(n, n, 21)
+    X = torch.from_numpy(unit_rows(2100, n, 22)).cuda()
+    h = prepare(kd, A, dtype)
+    eps, s_max, J, K = 0.08, 40, 24, 3
+    big = kd.kerdock_sparse_apply(h, X, eps, s_max, J, K, 5, t0=1000, debug=True)
+    for lo, hi in [(0, 1), (7, 12), (2000, 2100)]:
+        part = kd.kerdock_sparse_apply(h, X[lo:hi], eps, s_max, J, K, 5, t0=1000 + lo, debug=True)
+        for u, v in zip(big[:3], part[:3]):
+            assert torch.equal(u[lo:hi], v)
+        for key in ("mu", "survivors", "values"):
+            assert torch.equal(big[3][key][lo:hi], part[3][key])
+    h.destroy()
+
+
 def test_deterministic(orc):
     kd = need_gpu()
     A = rand_A(256, 256, 5)
@@ -242,6 +272,8 @@ def test_errors(orc):
     h = kd.kerdock_prepare(A)
     X = torch.from_numpy(unit_rows(2, 32, 1)).cuda()
     for kw, code in [(dict(eps=0.0, s_max=4, J=2, K=2), -1), (dict(eps=0.1, s_max=33, J=2, K=2), -1),
+                     (dict(eps=0.1, s_max=4, J=2, K=2, chunk=-1), -1),
+                     (dict(eps=0.1, s_max=4, J=2, K=2, chunk=1025), -1),
                      (dict(eps=0.1, s_max=4, J=0, K=2), -1), (dict(eps=0.1, s_max=4, J=2, K=33), -1),
                      (dict(eps=float("nan"), s_max=4, J=2, K=2), -1)]:
         with pytest.raises(kd.KerdockError) as e:
