@@ -51,13 +51,14 @@ def _load():
         "ko_table": (None, [c_p, c_i, c_i, c_p]),
         "ko_philox4x64_10": (None, [c_p, c_p, c_p]),
         "ko_draw_samples": (None, [c_u64, c_i64, c_i64, c_i64, c_p]),
+        "ko_draw_samples_stream": (None, [c_u64, c_i64, c_u64, c_i64, c_i64, c_p]),
         "ko_quant_bf16": (c_d, [c_d]),
         "ko_quant_e4m3": (c_d, [c_d]),
         "ko_sign_words": (None, [c_i, c_u64, c_p]),
         "ko_table_entries": (None, [c_p, c_i, c_i, c_p, c_i64, c_p, c_i, c_p]),
         "ko_mu_rows": (None, [c_p, c_i, c_i, c_p, c_p, c_i, c_i, c_p, c_i, c_i, c_p]),
         "ko_sparse_apply": (c_i, [c_p, c_i, c_i, c_p, c_i, c_i64, c_u64, c_i, c_i, c_d, c_i,
-                                  c_d, c_i, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p]),
+                                  c_d, c_i, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_i]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -140,9 +141,14 @@ def philox4x64_10(ctr, key):
     return out
 
 
-def draw_samples(seed, t, N, L):
+def draw_samples(seed, t, N, L, stream=None):
+    """Draws of stream position t; stream=None is the per-vector stream
+    (counter word 1 = 0), an integer w selects counter word 1 = w."""
     out = np.zeros(int(N), dtype=np.int64)
-    _load().ko_draw_samples(int(seed), int(t), int(N), int(L), _ptr(out))
+    if stream is None:
+        _load().ko_draw_samples(int(seed), int(t), int(N), int(L), _ptr(out))
+    else:
+        _load().ko_draw_samples_stream(int(seed), int(t), int(stream), int(N), int(L), _ptr(out))
     return out
 
 
@@ -191,7 +197,7 @@ def mu_rows(A, x, samples, J, K, rows, table_mode="exact"):
 TABLE_MODES = {"f32": 0, "exact": 0, "bf16": 1, "fp8": 2, "fp8e4m3": 2}
 
 
-def sparse_apply(A, X, J, K, eps, s_max, seed, t0=0, tau=0.0, table_mode="exact", debug=False):
+def sparse_apply(A, X, J, K, eps, s_max, seed, t0=0, tau=0.0, table_mode="exact", debug=False, tile=0):
     """Algorithm 1's streaming step for every row of X, in FP64.
 
     Returns a dict with out_idx (B, s_max), out_val, out_cnt and, with
@@ -216,7 +222,7 @@ def sparse_apply(A, X, J, K, eps, s_max, seed, t0=0, tau=0.0, table_mode="exact"
         _ptr(A), m, n, _ptr(X), B, int(t0), int(seed), int(J), int(K), float(eps), int(s_max),
         float(tau), TABLE_MODES[table_mode], _ptr(r["out_idx"]), _ptr(r["out_val"]),
         _ptr(r["out_cnt"]), _ptr(r.get("samples")), _ptr(r.get("coef")), _ptr(r.get("ybar")),
-        _ptr(r.get("mu")), _ptr(r.get("surv")))
+        _ptr(r.get("mu")), _ptr(r.get("surv")), int(tile))
     if rc != 0:
         raise ValueError("oracle sparse_apply rejected its arguments")
     return r

@@ -268,17 +268,26 @@ void ko_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64
 }
 
 /* Algorithm 1, streaming step: N indices drawn uniformly from [L] for the
- * vector with stream position t.  l = floor(r * L / 2^64). */
-void ko_draw_samples(uint64_t seed, int64_t t, int64_t N, int64_t L, int64_t *l_out)
+ * vector with stream position t.  l = floor(r * L / 2^64), r = word j mod 4
+ * of Philox4x64-10 at counter (floor(j/4), t, w, 0), key (seed, 0); w = 0
+ * for draws of one vector, w = 1 for draws shared by a group of vectors
+ * (the draws do not depend on x, so each vector of the group still sees
+ * independent uniform draws). */
+void ko_draw_samples_stream(uint64_t seed, int64_t t, uint64_t w, int64_t N, int64_t L, int64_t *l_out)
 {
     const uint64_t key[2] = { seed, 0 };
     for (int64_t j = 0; j < N; j++) {
-        uint64_t ctr[4] = { (uint64_t)(j / 4), (uint64_t)t, 0, 0 }, r[4];
+        uint64_t ctr[4] = { (uint64_t)(j / 4), (uint64_t)t, w, 0 }, r[4];
         ko_philox4x64_10(ctr, key, r);
         uint64_t hi, lo;
         mul_hi_lo(r[j % 4], (uint64_t)L, &hi, &lo);
         l_out[j] = (int64_t)hi;
     }
+}
+
+void ko_draw_samples(uint64_t seed, int64_t t, int64_t N, int64_t L, int64_t *l_out)
+{
+    ko_draw_samples_stream(seed, t, 0, N, L, l_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -428,6 +437,10 @@ void ko_mu_rows(const double *A, int m, int n, const double *x, const int64_t *l
  *   multiplied back, where the row scale is the FP32 rounding of
  *   max(||a_i||_1, sqrt(d) ||a_i||_inf) / 448 (a bound on every |A s_l|_i).
  *
+ * tile: 0 = every vector draws its own indices; tile > 0 = rows t of X with
+ *   the same floor(t / tile) = g share the draws of stream position t0 + g
+ *   (counter word 1 = 1), everything else unchanged.
+ *
  * Outputs (optional ones may be NULL):
  *   out_idx[B][s_max] (padding -1), out_val[B][s_max] (padding 0), out_cnt[B];
  *   dbg_samples[B][N] the drawn l_j; dbg_coef[B][N] the s_lj^T x;
@@ -439,9 +452,9 @@ int ko_sparse_apply(const double *A, int m, int n, const double *X, int B, int64
                     int table_mode,
                     int32_t *out_idx, double *out_val, int32_t *out_cnt,
                     int64_t *dbg_samples, double *dbg_coef, double *dbg_ybar,
-                    double *dbg_mu, int32_t *dbg_surv)
+                    double *dbg_mu, int32_t *dbg_surv, int tile)
 {
-    if (m < 1 || n < 1 || B < 0 || J < 1 || K < 1 || s_max < 1 || s_max > m || !(eps > 0))
+    if (m < 1 || n < 1 || B < 0 || J < 1 || K < 1 || s_max < 1 || s_max > m || !(eps > 0) || tile < 0)
         return -1;
     int k = ko_choose_k(n);
     int64_t d = (int64_t)1 << k;
@@ -472,7 +485,8 @@ int ko_sparse_apply(const double *A, int m, int n, const double *X, int B, int64
         double *kv = (double *)malloc(sizeof(double) * (size_t)K);
         int *order = (int *)malloc(sizeof(int) * (size_t)m);
 
-        ko_draw_samples(seed, t0 + t, N, L, ls);
+        if (tile > 0) ko_draw_samples_stream(seed, t0 + t / tile, 1, N, L, ls);
+        else ko_draw_samples(seed, t0 + t, N, L, ls);
         for (int64_t j = 0; j < N; j++) {
             ko_design_vector(n, k, ls[j], s);
             double c = 0.0;

@@ -319,6 +319,60 @@ def test_draw_samples_mapping(orc, k):
     assert ls.min() >= 0 and ls.max() < L
 
 
+def test_shared_draw_stream(orc):
+    """Shared draws: counter (floor(j/4), g, 1, 0) for group g, against
+    numpy's Philox; per-vector draws are the w = 0 stream."""
+    L = orc.design_size(10)
+    seed, g, N = 7, 42, 23
+    ls = orc.draw_samples(seed, g, N, L, stream=1)
+    for j in range(N):
+        r = int(_numpy_philox_block([j // 4, g, 1, 0], [seed, 0])[j % 4])
+        assert ls[j] == (r * L) >> 64
+    assert np.array_equal(orc.draw_samples(seed, g, N, L, stream=0), orc.draw_samples(seed, g, N, L))
+    assert not np.array_equal(ls, orc.draw_samples(seed, g, N, L))
+
+
+def test_shared_tiles_in_sparse_apply(orc):
+    """tile = T: rows t of one group floor(t / T) = g use the draws of
+    position t0 + g on the shared stream; every other step is per vector."""
+    rng = np.random.default_rng(8)
+    m, n, J, K, T, t0 = 12, 16, 5, 3, 4, 9
+    A = rng.standard_normal((m, n))
+    X = rng.standard_normal((10, n))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    r = orc.sparse_apply(A, X, J, K, 0.3, 6, seed=3, t0=t0, debug=True, tile=T)
+    L = orc.design_size(orc.choose_k(n))
+    for t in range(10):
+        assert np.array_equal(r["samples"][t], orc.draw_samples(3, t0 + t // T, J * K, L, stream=1))
+    # each vector's estimate is the per-vector estimator on those draws: the
+    # coefficients and batch means by brute force
+    k = orc.choose_k(n)
+    for t in (0, 5, 9):
+        ls = r["samples"][t]
+        S = np.stack([orc.design_vector(n, k, l) for l in ls])
+        c = S @ X[t]
+        assert np.allclose(r["coef"][t], c, rtol=1e-13, atol=1e-13)
+        Y = (A @ S.T) * c[None, :]
+        ybar = Y.reshape(m, K, J).mean(axis=2).T
+        assert np.allclose(r["ybar"][t], ybar, rtol=1e-12, atol=1e-12)
+        assert np.allclose(r["mu"][t], np.median(ybar, axis=0), rtol=1e-12, atol=1e-12)
+
+
+def test_theorem5_with_shared_draws(orc):
+    """The guarantee is per vector, so it survives sharing the draws within
+    a group: failure rate <= eta with Theorem 5's J and K."""
+    from paper_2105_05879_amd import workloads
+    import math
+    w = workloads.near_sparse(batch=256, m=12, n=16, s=2, delta=0.05)
+    eta = 0.1
+    gamma = 0.5 * (w.eps - w.delta)
+    J = math.ceil(4 * math.e ** 2 * float(np.max((w.A.astype(np.float64) ** 2).sum(1))) / gamma ** 2)
+    K = math.ceil(2 * math.log(w.A.shape[0] / eta))
+    r = orc.sparse_apply(w.A, w.X, J, K, w.eps, w.s, seed=78, tau=0.5 * (w.eps + w.delta), tile=64)
+    fails = sum(not np.array_equal(r["out_idx"][t][:r["out_cnt"][t]], w.supports[t]) for t in range(w.batch))
+    assert fails <= eta * w.batch
+
+
 def test_draw_samples_uniform(orc):
     """chi-square test of the (basis, vector) coordinates at k = 4."""
     k, d = 4, 16
