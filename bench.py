@@ -305,6 +305,35 @@ def paper_form(kd, torch, np, workloads, args):
         log("paper regime %s: prepare %.1f s, %.0f x/s batched (gather %.3f ms %.0f GB/s, select "
             "%.3f, survivors %.3f), %.0f x/s one per call, exact %d/%d"
             % (dt, prep, res[dt]["x_per_s"], kern[1], gbps, kern[2], kern[3], single, exact, B))
+        # shared-draw form: one draw list per group of 64 vectors, batch sums
+        # as a matrix product
+        for sidx in range(args.warmup):
+            kd.kerdock_sparse_apply_shared(h, X, w.eps, S, J, K, 2021, t0=sidx * B // 64, out=out)
+        torch.cuda.synchronize()
+        kern = np.zeros(4)
+        t0 = time.perf_counter()
+        for sidx in range(args.steps):
+            kd.kerdock_sparse_apply_shared(h, X, w.eps, S, J, K, 2021, t0=sidx * B // 64, out=out, kernel_ms=ms)
+            kern += np.array(ms[:4])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern /= args.steps
+        idx, val, cnt = (o.cpu().numpy() for o in out)
+        exact = 0
+        for t in range(B):
+            sup = w.supports[t]
+            if cnt[t] == len(sup) and np.array_equal(idx[t][:cnt[t]], sup) and np.allclose(
+                    val[t][:cnt[t]], Y[t][sup], rtol=1e-5, atol=1e-7):
+                exact += 1
+        flops = 2.0 * h.info.m * J * K * B
+        res[dt]["shared"] = {"x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+                             "exact_recovery": exact / B,
+                             "kernel_ms": {"coef": kern[0], "gemm": kern[1], "select": kern[2],
+                                           "survivors": kern[3]},
+                             "gemm_TFLOPs": flops / (kern[1] * 1e-3) / 1e12}
+        log("paper regime %s shared draws: %.0f x/s (coef %.3f ms, gemm %.3f ms = %.1f TFLOP/s, select %.3f, "
+            "survivors %.3f), exact %d/%d" % (dt, res[dt]["shared"]["x_per_s"], kern[0], kern[1],
+                                               res[dt]["shared"]["gemm_TFLOPs"], kern[2], kern[3], exact, B))
         h.destroy()
         torch.cuda.empty_cache()
     base = dense_baselines(torch, A, X)

@@ -294,6 +294,28 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
                           int32_t *out_cnt, int32_t *fallback, void *stream);
 
 /*
+ * kerdock_sparse_apply_shared -- the streaming step with draws shared by
+ * groups of KERDOCK_SHARED_TILE consecutive rows of X.  Rows t with the same
+ * g = floor(t / KERDOCK_SHARED_TILE) use the N = J K indices drawn at stream
+ * position t0 + g of a second Philox stream (counter (floor(j/4), t0 + g, 1,
+ * 0), key (seed, 0)).  The draws never depend on x, so for every single x
+ * they are N independent uniform draws as in Algorithm 1 and Theorem 5's
+ * bound holds per x (the events of two vectors of one group are no longer
+ * independent).  With one draw list per group the batch sums become the
+ * matrix product of the gathered table columns and the coefficient block of
+ * the group, which reads each drawn column once per group.  Arguments,
+ * outputs, errors and the debug outputs are those of kerdock_sparse_apply
+ * (dbg_samples row t holds its group's draws); params->chunk is ignored (the
+ * batch sums are accumulated by the matrix cores), J K must stay below 2^26,
+ * and kernel_ms receives [0] draws + coefficients, [1] matrix product,
+ * [2] median and selection, [3] survivor dots and threshold.
+ */
+#define KERDOCK_SHARED_TILE 64
+int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                                const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                                int32_t *out_cnt, void *stream);
+
+/*
  * kerdock_theory_params -- the streaming parameters of Theorem 5 for a target
  * failure probability eta (0 < eta < 1) and x in Sigma(A, s, delta):
  * gamma = (eps - delta) / 2, J = ceil(4 e^2 |A|_{2->inf}^2 / gamma^2),

@@ -30,6 +30,11 @@ int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int 
 int gather_chunk_max();
 int launch_select(const SelArgs &a, int batch, hipStream_t s);
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
+int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs, uint64_t seed,
+                       int64_t t0, int N, uint32_t *ell, float *coef, uint32_t *dbg_samples, float *dbg_coef,
+                       hipStream_t s);
+int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch, int J, int K, const uint32_t *ell,
+                       const float *coef, float *partial, hipStream_t s);
 
 static thread_local std::string g_error;
 
@@ -146,9 +151,10 @@ static void cache_store(const kerdock_handle_s *h, int K) {
 
 // The streaming step for every row of X; rows t with active[t] == 0 (when
 // active is given) are skipped by every kernel and their outputs untouched.
-int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
-                   const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
-                   const int32_t *active, void *stream) {
+// Argument checks shared by the streaming entry points; 1 = nothing to do.
+static int check_apply_args(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                            const kerdock_apply_params *p, const int32_t *out_idx, const float *out_val,
+                            const int32_t *out_cnt) {
     if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
     if (!p) return fail(KERDOCK_ERR_INVALID_ARG, "params is NULL");
     if (batch < 0) return fail(KERDOCK_ERR_INVALID_ARG, "batch < 0");
@@ -159,9 +165,21 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
         return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
     if (p->chunk < 0 || p->chunk > gather_chunk_max())
         return fail(KERDOCK_ERR_INVALID_ARG, "chunk must lie in [0, 1024]");
-    if (batch == 0) return KERDOCK_OK;
+    if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
+        return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
+    if (batch == 0) return 1;
     if (!X || !out_idx || !out_val || !out_cnt)
         return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
+    return KERDOCK_OK;
+}
+
+int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                   const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
+                   const int32_t *active, void *stream) {
+    {
+        const int c = check_apply_args(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt);
+        if (c != KERDOCK_OK) return c == 1 ? KERDOCK_OK : c;
+    }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int J = p->J, K = p->K, N = J * K;
     const int chunk = chunk_for(h, J, p->chunk);
@@ -175,8 +193,6 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
     float *svals = reinterpret_cast<float *>(ws + lay.svals);
-    if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
-        return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
 
     // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
     // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
@@ -404,6 +420,62 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
                          const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
                          int32_t *out_cnt, void *stream) {
     return kd::apply_internal(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, nullptr, stream);
+}
+
+int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                                const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                                int32_t *out_cnt, void *stream) {
+    {
+        const int c = check_apply_args(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt);
+        if (c != KERDOCK_OK) return c == 1 ? KERDOCK_OK : c;
+    }
+    const int J = p->J, K = p->K, N = J * K;
+    if (N > (1 << 26)) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: J K must stay below 2^26");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t groups = ((size_t)batch + KERDOCK_SHARED_TILE - 1) / KERDOCK_SHARED_TILE;
+    size_t off = 0;
+    const size_t o_partial = off; off += align256((size_t)batch * K * h->pitch * 4);
+    const size_t o_coef = off;    off += align256(groups * KERDOCK_SHARED_TILE * N * 4);
+    const size_t o_ell = off;     off += align256(groups * N * 4);
+    const size_t o_surv = off;    off += align256((size_t)batch * s_max * 4);
+    const size_t o_nsurv = off;   off += align256((size_t)batch * 4);
+    const size_t o_svals = off;   off += align256((size_t)batch * s_max * 4);
+    int rc = ensure_workspace(h, off);
+    if (rc != KERDOCK_OK) return rc;
+    char *ws = reinterpret_cast<char *>(h->ws);
+    float *partial = reinterpret_cast<float *>(ws + o_partial);
+    float *coef = reinterpret_cast<float *>(ws + o_coef);
+    uint32_t *ell = reinterpret_cast<uint32_t *>(ws + o_ell);
+    int32_t *surv = reinterpret_cast<int32_t *>(ws + o_surv);
+    int32_t *nsurv = reinterpret_cast<int32_t *>(ws + o_nsurv);
+    float *svals = reinterpret_cast<float *>(ws + o_svals);
+
+    // kernel_ms: [0] draws + coefficients, [1] matrix product, [2] select,
+    // [3] survivors
+    const bool timed = p->kernel_ms != nullptr;
+    if (timed && !h->ev[0])
+        for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
+    if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
+    rc = launch_shared_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, ell, coef, p->dbg_samples,
+                            p->dbg_coef, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
+    if (rc == KERDOCK_OK) rc = launch_shared_gemm(h->dtype, h->table, h->pitch, batch, J, K, ell, coef, partial, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
+    SelArgs sa{partial, h->m, h->pitch, K, 1, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, nullptr};
+    if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
+    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, nullptr, nullptr,
+                svals, surv_vec4(X, h->n)};
+    if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
+    if (rc != KERDOCK_OK) return rc;
+    if (timed) {
+        KD_HIP(hipEventSynchronize(h->ev[4]));
+        for (int q = 0; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
+    }
+    if (p->dbg_survivors)
+        KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
+    return KERDOCK_OK;
 }
 
 int kerdock_theory_params(kerdock_handle h, float eps, float delta, float eta, int32_t *J, int32_t *K,

@@ -137,32 +137,20 @@ struct DGArgs {
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
 };
 
-template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
-__device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int seg, int nchunks,
-                                            uint32_t *s_ell, float *s_coef, float *red) {
-    const unsigned char *__restrict__ table = a.table;
-    const int col_bytes = a.col_bytes, n = a.n, k = a.k, N = a.N, J = a.J, chunk = a.chunk;
-    const int chunks_per_batch = a.chunks_per_batch, groups = a.groups, tpc = a.tpc, pitch = a.pitch;
-    const float *__restrict__ X = a.X;
-    const int64_t L = a.L;
-    const uint32_t *__restrict__ signs = a.signs;
-    const uint64_t seed = a.seed;
-    const int64_t t0 = a.t0_dev ? *a.t0_dev : a.t0;
-    float *__restrict__ partial = a.partial;
-    uint32_t *__restrict__ dbg_samples = a.dbg_samples;
-    float *__restrict__ dbg_coef = a.dbg_coef;
-    constexpr int E = Elems<DT>::N;
-    if (a.active && !a.active[t]) return;      // uniform over the workgroup
-    const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
-    const int jbeg = kb * J + cj * chunk;
-    const int cnt = min(chunk, (kb + 1) * J - jbeg);
+// Draws jbeg .. jbeg + cnt - 1 (cnt <= MAX_CHUNK) of the Philox stream with
+// counter words (floor(j/4), pos, word2, 0) and their coefficients s_l^T x,
+// into s_ell / s_coef; all four waves of the workgroup take part, and the
+// caller synchronises before reading them.  The method is described at
+// draw_gather below.
+template <int P>
+__device__ __forceinline__ void draws_coefs(const float *__restrict__ x, int n, int k, int64_t L,
+                                            const uint32_t *__restrict__ signs, uint64_t seed, uint64_t pos,
+                                            uint64_t word2, int jbeg, int cnt, uint32_t *s_ell,
+                                            float *s_coef) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // ---------------------------------------------------------- phase 1
     {
         const int d = 1 << k;
         const int words = d >= 32 ? d / 32 : 1;
-        const float *x = X + (size_t)t * n;
         float xf[P][32];
         float asum = 0.f;
 #pragma unroll
@@ -196,7 +184,7 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
             uint32_t my_l = 0;
             if (lane < jn) {
                 const int j = jbeg + r0 + lane;
-                uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + t), 0, 0};
+                uint64_t c4[4] = {(uint64_t)(j >> 2), pos, word2, 0};
                 philox4x64_10(c4, seed, 0);
                 const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
                 my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
@@ -214,6 +202,35 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
                         sw[u][p] = ((int)b < d / 2 && word < words) ? signs[(size_t)b * words + word] : 0u;
                     }
                 }
+                // per-lane partial sums of the four draws, then one
+                // transposed butterfly for all four: bits 5 and 4 of the lane
+                // pick the draw, bits 3..0 finish the sums (exact integers)
+                int part[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t w = lq[u] & (uint32_t)(d - 1);
+                    const uint32_t wlo = walsh32(w & 31u);
+                    int acc = 0;
+#pragma unroll
+                    for (int p = 0; p < P; ++p) {
+                        const uint32_t word = (uint32_t)(lane + 64 * p);
+                        if ((int)word < words) {
+                            const uint32_t par = __popc(word & (w >> 5)) & 1u;
+                            const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
+#pragma unroll
+                            for (int q = 0; q < 32; ++q)
+                                acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
+                            acc += __popc(mask);
+                        }
+                    }
+                    part[u] = acc;
+                }
+                const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+                const int k0 = (h5 ? part[2] : part[0]) + __shfl_xor(h5 ? part[0] : part[2], 32);
+                const int k1 = (h5 ? part[3] : part[1]) + __shfl_xor(h5 ? part[1] : part[3], 32);
+                int z = (h4 ? k1 : k0) + __shfl_xor(h4 ? k0 : k1, 16);
+#pragma unroll
+                for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (jj0 + u >= jn) break;
@@ -222,22 +239,8 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
                     if ((int)b == d / 2) {
                         c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
                     } else {
-                        const uint32_t wlo = walsh32(w & 31u);
-                        int acc = 0;
-#pragma unroll
-                        for (int p = 0; p < P; ++p) {
-                            const uint32_t word = (uint32_t)(lane + 64 * p);
-                            if ((int)word < words) {
-                                const uint32_t par = __popc(word & (w >> 5)) & 1u;
-                                const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
-#pragma unroll
-                                for (int q = 0; q < 32; ++q)
-                                    acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
-                                acc += __popc(mask);
-                            }
-                        }
-                        acc = wave_sum_i32(acc);
-                        c = finite ? (float)acc * down : __builtin_nanf("");
+                        const int tot = __builtin_amdgcn_readlane(z, ((u >> 1) << 5) | ((u & 1) << 4));
+                        c = finite ? (float)tot * down : __builtin_nanf("");
                     }
                     if (lane == jj0 + u) my_c = c;
                 }
@@ -245,14 +248,41 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
             if (lane < jn) {
                 s_ell[r0 + lane] = my_l;
                 s_coef[r0 + lane] = my_c;
-                if (dbg_samples && seg == 0) {
-                    dbg_samples[(size_t)t * N + jbeg + r0 + lane] = my_l;
-                    dbg_coef[(size_t)t * N + jbeg + r0 + lane] = my_c;
-                }
             }
         }
     }
+
+}
+
+template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
+__device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int seg, int nchunks,
+                                            uint32_t *s_ell, float *s_coef, float *red) {
+    const unsigned char *__restrict__ table = a.table;
+    const int col_bytes = a.col_bytes, n = a.n, k = a.k, N = a.N, J = a.J, chunk = a.chunk;
+    const int chunks_per_batch = a.chunks_per_batch, groups = a.groups, tpc = a.tpc, pitch = a.pitch;
+    const float *__restrict__ X = a.X;
+    const int64_t L = a.L;
+    const uint32_t *__restrict__ signs = a.signs;
+    const uint64_t seed = a.seed;
+    const int64_t t0 = a.t0_dev ? *a.t0_dev : a.t0;
+    float *__restrict__ partial = a.partial;
+    uint32_t *__restrict__ dbg_samples = a.dbg_samples;
+    float *__restrict__ dbg_coef = a.dbg_coef;
+    constexpr int E = Elems<DT>::N;
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
+    const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
+    const int jbeg = kb * J + cj * chunk;
+    const int cnt = min(chunk, (kb + 1) * J - jbeg);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // ---------------------------------------------------------- phase 1
+    draws_coefs<P>(X + (size_t)t * n, n, k, L, signs, seed, (uint64_t)(t0 + t), 0, jbeg, cnt, s_ell, s_coef);
     __syncthreads();
+    if (dbg_samples && seg == 0)
+        for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS) {
+            dbg_samples[(size_t)t * N + jbeg + r] = s_ell[r];
+            dbg_coef[(size_t)t * N + jbeg + r] = s_coef[r];
+        }
 
     // ---------------------------------------------------------- phase 2
     const int g = GROUPED ? (int)threadIdx.x / tpc : 0;

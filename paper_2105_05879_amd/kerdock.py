@@ -27,6 +27,9 @@ class KerdockError(RuntimeError):
         self.code = code
 
 
+SHARED_TILE = 64      # KERDOCK_SHARED_TILE
+
+
 class ApplyParams(ctypes.Structure):
     _fields_ = [("J", ctypes.c_int32), ("K", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("t0", ctypes.c_int64), ("tau", ctypes.c_float),
@@ -75,6 +78,10 @@ EXPORTS = {
     "kerdock_learned_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                                              ctypes.c_int, ctypes.POINTER(ApplyParams), ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_sparse_apply_shared": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                   ctypes.c_float, ctypes.c_int,
+                                                   ctypes.POINTER(ApplyParams), ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kerdock_theory_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
@@ -192,14 +199,8 @@ def kerdock_reserve(h, batch, J, K, s_max):
     _check(lib().kerdock_reserve(h.ptr, batch, J, K, s_max))
 
 
-def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
-                         stream=None, kernel_ms=None, chunk=0):
-    """h_eps(Ax) on the s_max rows of largest median-of-means estimate.
-
-    Returns (idx [B, s_max] int32, val [B, s_max] f32, cnt [B] int32) and,
-    with debug=True, a dict of samples, coef, mu, survivors, values.
-    kernel_ms: optional (ctypes.c_float * 4)() that receives the durations
-    of the four kernels, timed with HIP events on the call's stream."""
+def _sparse_apply(entry, h, X, eps, s_max, J, K, seed, t0, tau, out, debug, stream, kernel_ms, chunk):
+    """Shared body of the two streaming entry points."""
     B = X.shape[0]
     dev = X.device
     if out is None:
@@ -223,13 +224,34 @@ def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, 
         p.dbg_mu = dbg["mu"].data_ptr()
         p.dbg_survivors = dbg["survivors"].data_ptr()
         p.dbg_values = dbg["values"].data_ptr()
-    _check(lib().kerdock_sparse_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max,
-                                      ctypes.byref(p), _dev(idx, torch.int32, "idx"),
-                                      _dev(val, torch.float32, "val"), _dev(cnt, torch.int32, "cnt"),
-                                      _stream(stream)))
+    _check(getattr(lib(), entry)(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max,
+                                 ctypes.byref(p), _dev(idx, torch.int32, "idx"),
+                                 _dev(val, torch.float32, "val"), _dev(cnt, torch.int32, "cnt"),
+                                 _stream(stream)))
     if debug:
         return idx, val, cnt, dbg
     return idx, val, cnt
+
+
+def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
+                         stream=None, kernel_ms=None, chunk=0):
+    """h_eps(Ax) on the s_max rows of largest median-of-means estimate.
+
+    Returns (idx [B, s_max] int32, val [B, s_max] f32, cnt [B] int32) and,
+    with debug=True, a dict of samples, coef, mu, survivors, values.
+    kernel_ms: optional (ctypes.c_float * 4)() that receives the durations
+    of the four kernels, timed with HIP events on the call's stream."""
+    return _sparse_apply("kerdock_sparse_apply", h, X, eps, s_max, J, K, seed, t0, tau, out, debug, stream,
+                         kernel_ms, chunk)
+
+
+def kerdock_sparse_apply_shared(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
+                                stream=None, kernel_ms=None):
+    """As kerdock_sparse_apply, with the draws shared by groups of
+    SHARED_TILE consecutive rows of X (stream position t0 + group);
+    kernel_ms: [coefficients, matrix product, select, survivors]."""
+    return _sparse_apply("kerdock_sparse_apply_shared", h, X, eps, s_max, J, K, seed, t0, tau, out, debug,
+                         stream, kernel_ms, 0)
 
 
 def kerdock_read_columns(h, ells, stream=None):
