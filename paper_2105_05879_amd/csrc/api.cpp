@@ -31,8 +31,9 @@ int gather_chunk_max();
 int launch_select(const SelArgs &a, int batch, hipStream_t s);
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
 int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs, uint64_t seed,
-                       int64_t t0, int N, uint32_t *ell, float *coef, uint32_t *dbg_samples, float *dbg_coef,
-                       hipStream_t s);
+                       int64_t t0, int N, int8_t *digits, int2 *xscale, uint32_t *ell, float *coef,
+                       uint32_t *dbg_samples, float *dbg_coef, hipStream_t s);
+int shared_n_pad(int n);
 int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch, int J, int K, const uint32_t *ell,
                        const float *coef, float *partial, hipStream_t s);
 
@@ -440,6 +441,8 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     const size_t o_surv = off;    off += align256((size_t)batch * s_max * 4);
     const size_t o_nsurv = off;   off += align256((size_t)batch * 4);
     const size_t o_svals = off;   off += align256((size_t)batch * s_max * 4);
+    const size_t o_digits = off;  off += align256((size_t)batch * 4 * shared_n_pad(h->n));
+    const size_t o_xscale = off;  off += align256((size_t)batch * 8);
     int rc = ensure_workspace(h, off);
     if (rc != KERDOCK_OK) return rc;
     char *ws = reinterpret_cast<char *>(h->ws);
@@ -449,6 +452,8 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     int32_t *surv = reinterpret_cast<int32_t *>(ws + o_surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + o_nsurv);
     float *svals = reinterpret_cast<float *>(ws + o_svals);
+    int8_t *digits = reinterpret_cast<int8_t *>(ws + o_digits);
+    int2 *xscale = reinterpret_cast<int2 *>(ws + o_xscale);
 
     // kernel_ms: [0] draws + coefficients, [1] matrix product, [2] select,
     // [3] survivors
@@ -456,8 +461,8 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     if (timed && !h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
     if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
-    rc = launch_shared_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, ell, coef, p->dbg_samples,
-                            p->dbg_coef, s);
+    rc = launch_shared_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, digits, xscale, ell, coef,
+                            p->dbg_samples, p->dbg_coef, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
     if (rc == KERDOCK_OK) rc = launch_shared_gemm(h->dtype, h->table, h->pitch, batch, J, K, ell, coef, partial, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));

@@ -137,6 +137,36 @@ struct DGArgs {
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
 };
 
+// x in fixed point, x_int = rint(x 2^E2) with sum |x_int| <= 2^30 (so every
+// signed sum of x_int is an exact int32); lane `lane` of one wave holds the
+// elements (lane + 64 p) * 32 + q, q < 32, zero beyond n.  finite is false
+// when x holds an inf or NaN (then x_int = 0).
+template <int P>
+__device__ __forceinline__ void fixed_point(const float *__restrict__ x, int n, int lane, int (&xi)[P][32], int &E2,
+                                            bool &finite) {
+    float xf[P][32];
+    float asum = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int e = (lane + 64 * p) * 32 + q;
+            xf[p][q] = e < n ? x[e] : 0.f;
+            asum += fabsf(xf[p][q]);
+        }
+    asum = wave_sum_f32(asum);
+    // scale 2^E2 with asum 2^E2 <= 2^30: asum < 2^(ea + 1), E2 = 29 - ea
+    finite = asum < INFINITY;          // false for inf and NaN
+    E2 = 0;
+    if (finite && asum > 0.f) E2 = 29 - ((int)((__float_as_uint(asum) >> 23) & 0xFF) - 127);
+    E2 = max(-120, min(E2, 120));
+    const float up = ldexpf(1.0f, E2);
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
+}
+
 // Draws jbeg .. jbeg + cnt - 1 (cnt <= MAX_CHUNK) of the Philox stream with
 // counter words (floor(j/4), pos, word2, 0) and their coefficients s_l^T x,
 // into s_ell / s_coef; all four waves of the workgroup take part, and the
@@ -151,28 +181,11 @@ __device__ __forceinline__ void draws_coefs(const float *__restrict__ x, int n, 
     {
         const int d = 1 << k;
         const int words = d >= 32 ? d / 32 : 1;
-        float xf[P][32];
-        float asum = 0.f;
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int e = (lane + 64 * p) * 32 + q;
-                xf[p][q] = e < n ? x[e] : 0.f;
-                asum += fabsf(xf[p][q]);
-            }
-        asum = wave_sum_f32(asum);
-        // scale 2^E2 with asum 2^E2 <= 2^30: asum < 2^(ea + 1), E2 = 29 - ea
-        const bool finite = asum < INFINITY;          // false for inf and NaN
-        int E2 = 0;
-        if (finite && asum > 0.f) E2 = 29 - ((int)((__float_as_uint(asum) >> 23) & 0xFF) - 127);
-        E2 = max(-120, min(E2, 120));
-        const float up = ldexpf(1.0f, E2), down = ldexpf(1.0f, -E2);
         int xi[P][32];
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
+        int E2;
+        bool finite;
+        fixed_point<P>(x, n, lane, xi, E2, finite);
+        const float down = ldexpf(1.0f, -E2);
         const float sqrt_d = sqrtf((float)d);
 
         // the four waves take equal runs of the chunk's draws (a multiple of

@@ -17,35 +17,172 @@
 
 namespace kd {
 
+// coordinates of the digit rows: n rounded up to a multiple of 32
+int shared_n_pad(int n) { return (n + 31) / 32 * 32; }
+
 constexpr int ST = KERDOCK_SHARED_TILE;       // vectors per draw group
-constexpr int SH_CHUNK = MAX_CHUNK;           // draws per coefficient workgroup
 constexpr int SG_BM = 128;                    // table rows per GEMM workgroup
 constexpr int SG_BK = 32;                     // draws per LDS stage
 
-// k_shared_coef: grid (batch, ceil(N / SH_CHUNK)).  Vector t, draws jbeg ..
-// jbeg + cnt - 1 of its group: l_j to ell[g][j] (written by the group's first
-// vector), s_l^T x_t to coef[g][t mod 64][j].
+// ------------------------------------------------------- coefficients --
+// With one draw list per group the coefficients of a group form the product
+// C = S X_g of the N x n sign matrix S (rows s_l restricted to the first n
+// coordinates, entries +-1) and the n x 64 block of the group's vectors.  In
+// the fixed point of the per-vector form, x_int = rint(x 2^E2) with
+// sum |x_int| <= 2^30, each x_int is split into four balanced base-256 digits
+// in [-128, 127], and C is accumulated digit by digit on the int8 matrix cores
+// (16 x 16 x 32 MFMA, int32 accumulators): every step is integer arithmetic,
+// so c = (sum_b 256^b C_b) 2^-E2 equals the per-vector form's exact signed sum.
+// Identity draws (basis d/2) give sqrt(d) x[w] directly.
+
+// k_x_digits: grid (batch), one wave.  digits[t][b][q] (q < n_pad, zero
+// beyond n) and the scale exponent / finiteness of x_t.
 template <int P>
-__global__ __launch_bounds__(GATHER_THREADS) void k_shared_coef(const float *__restrict__ X, int n, int k, int64_t L,
-                                                                const uint32_t *__restrict__ signs, uint64_t seed,
-                                                                int64_t t0, int N, uint32_t *__restrict__ ell,
-                                                                float *__restrict__ coef,
-                                                                uint32_t *__restrict__ dbg_samples,
-                                                                float *__restrict__ dbg_coef) {
-    __shared__ uint32_t s_ell[SH_CHUNK];
-    __shared__ float s_coef[SH_CHUNK];
-    const int t = blockIdx.x, g = t / ST, tt = t % ST;
-    const int jbeg = blockIdx.y * SH_CHUNK;
-    const int cnt = min(SH_CHUNK, N - jbeg);
-    draws_coefs<P>(X + (size_t)t * n, n, k, L, signs, seed, (uint64_t)(t0 + g), 1, jbeg, cnt, s_ell, s_coef);
+__global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, int n, int n_pad,
+                                                 int8_t *__restrict__ digits, int2 *__restrict__ xscale) {
+    const int t = blockIdx.x, lane = threadIdx.x;
+    int xi[P][32];
+    int E2;
+    bool finite;
+    fixed_point<P>(X + (size_t)t * n, n, lane, xi, E2, finite);
+    int8_t *dt = digits + (size_t)t * 4 * n_pad;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int e0 = (lane + 64 * p) * 32;
+        if (e0 >= n_pad) continue;
+        uint32_t packed[4][8];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            int v = xi[p][q];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int dg = ((v & 255) ^ 128) - 128;        // balanced digit
+                v = (v - dg) >> 8;                              // exact
+                if (q % 4 == 0) packed[b][q / 4] = 0u;
+                packed[b][q / 4] |= (uint32_t)(uint8_t)dg << (8 * (q % 4));
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            uint32_t *dst = reinterpret_cast<uint32_t *>(dt + (size_t)b * n_pad + e0);
+#pragma unroll
+            for (int w = 0; w < 8; ++w) dst[w] = packed[b][w];
+        }
+    }
+    if (lane == 0) xscale[t] = make_int2(E2, finite ? 1 : 0);
+}
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// k_shared_coef: grid (ceil(N / 64), groups), 256 threads.  Wave w takes
+// draws j0 + 16 w .. + 15 of group g (the 16 rows of its MFMA blocks) against
+// the group's 64 vectors (4 column blocks) and 4 digits: 16 accumulators.
+// Per step of 32 coordinates the digits of the 64 vectors go through LDS;
+// the sign rows are made in registers from the sign bitmaps and the Walsh
+// pattern of w, eight coordinates (one 64-bit operand) per lane.
+__global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
+                                                     const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
+                                                     int batch, int N, const int8_t *__restrict__ digits,
+                                                     const int2 *__restrict__ xscale, uint32_t *__restrict__ ell,
+                                                     float *__restrict__ coef, uint32_t *__restrict__ dbg_samples,
+                                                     float *__restrict__ dbg_coef) {
+    __shared__ uint64_t lut[256];                   // 8 sign bits -> 8 bytes of +-1
+    __shared__ __align__(16) int8_t Bs[4][ST][32];  // [digit][vector][coordinate]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = blockIdx.y, nx = min(ST, batch - g * ST);
+    const int d = 1 << k, words = d >= 32 ? d / 32 : 1;
+    {
+        uint64_t v = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v |= (uint64_t)(((tid >> e) & 1) ? 0xFFu : 0x01u) << (8 * e);
+        lut[tid] = v;
+    }
+    // this lane's draw: row lane % 16 of the wave's block
+    const int row = lane & 15;
+    const int j = blockIdx.x * 64 + wave * 16 + row;
+    uint32_t my_l = 0;
+    if (j < N) {
+        uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + g), 1, 0};
+        philox4x64_10(c4, seed, 0);
+        const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
+        my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
+    }
+    const uint32_t bb = my_l >> k, ww = my_l & (uint32_t)(d - 1);
+    const bool kerdock_row = j < N && (int)bb < d / 2;
+    const uint32_t w8 = (ww & 1u ? 0xAAu : 0u) ^ (ww & 2u ? 0xCCu : 0u) ^ (ww & 4u ? 0xF0u : 0u);
+    const int kq = (lane >> 4) * 8;                  // this lane's 8 coordinates within a step
+
+    i32x4 acc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[b][c] = i32x4{0, 0, 0, 0};
     __syncthreads();
-    for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS) {
-        const size_t j = (size_t)jbeg + r;
-        coef[((size_t)g * ST + tt) * N + j] = s_coef[r];
-        if (tt == 0) ell[(size_t)g * N + j] = s_ell[r];
-        if (dbg_samples) {
-            dbg_samples[(size_t)t * N + j] = s_ell[r];
-            dbg_coef[(size_t)t * N + j] = s_coef[r];
+
+    for (int q0 = 0; q0 < n_pad; q0 += 32) {
+        {   // digits of the group's vectors: 32 bytes per (vector, digit)
+            const int tv = tid >> 2, b = tid & 3;
+            uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
+            if (tv < nx) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(
+                    digits + ((size_t)(g * ST + tv) * 4 + b) * n_pad + q0);
+                lo = src[0];
+                hi = src[1];
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(&Bs[b][tv][0]);
+            dst[0] = lo;
+            dst[1] = hi;
+        }
+        long a = 0;
+        if (kerdock_row) {
+            const int q = q0 + kq;
+            const uint32_t wd = signs[(size_t)bb * words + (q >> 5)];
+            const uint32_t par = __popc((uint32_t)q & ww) & 1u;
+            const uint32_t m8 = ((wd >> (q & 31)) & 0xFFu) ^ w8 ^ (par ? 0xFFu : 0u);
+            a = (long)lut[m8];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const long bop = *reinterpret_cast<const long *>(&Bs[b][c * 16 + row][kq]);
+                acc[b][c] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a, bop, acc[b][c], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+
+    // D block: lane holds draws 4 (lane / 16) + v of the wave's 16, vector
+    // column lane % 16 of block c
+    const float sqrt_d = sqrtf((float)d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 4 * (lane >> 4) + v;
+        const uint32_t l_r = __shfl(my_l, r);
+        const int jr = blockIdx.x * 64 + wave * 16 + r;
+        if (jr >= N) continue;
+        const uint32_t b_r = l_r >> k, w_r = l_r & (uint32_t)(d - 1);
+        const bool ident = (int)b_r == d / 2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int tv = c * 16 + row;
+            if (tv >= nx) continue;
+            const int t = g * ST + tv;
+            float cf;
+            if (ident) {
+                cf = ((int)w_r < n) ? sqrt_d * X[(size_t)t * n + w_r] : 0.f;
+            } else {
+                const int2 sc = xscale[t];
+                const int64_t tot = (int64_t)acc[0][c][v] + ((int64_t)acc[1][c][v] << 8) +
+                                    ((int64_t)acc[2][c][v] << 16) + ((int64_t)acc[3][c][v] << 24);
+                cf = sc.y ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
+            }
+            coef[(size_t)t * N + jr] = cf;
+            if (tv == 0) ell[(size_t)g * N + jr] = l_r;
+            if (dbg_samples) {
+                dbg_samples[(size_t)t * N + jr] = l_r;
+                dbg_coef[(size_t)t * N + jr] = cf;
+            }
         }
     }
 }
@@ -106,36 +243,45 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // Global loads of stage j0 + SG_BK are issued before the MFMAs of stage
+    // j0 and land in LDS after them (one LDS buffer, register prefetch).
+    constexpr int PASSES = SG_BK / CPP;
+    u32x4 ra[PASSES];
+    float rb[8];
+    const int bt = tid >> 2, bq = (tid & 3) * 8;
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
+            const int jj = j0 + cc;
+            ra[ps] = u32x4{0u, 0u, 0u, 0u};
+            if (jj < J && i0 + r < pitch) {
+                const unsigned char *src =
+                    table + (size_t)el[jj] * (size_t)col_bytes + (size_t)(i0 + r) * (size_t)(16 / E);
+                ra[ps] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src));
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int jj = j0 + bq + e;
+            rb[e] = (bt < nx && jj < J) ? cf[(size_t)bt * N + jj] : 0.f;
+        }
+    };
+    fetch(0);
     for (int j0 = 0; j0 < J; j0 += SG_BK) {
-        // A stage: SG_BK gathered column slices of SG_BM rows, 16 bytes a thread
 #pragma unroll
-        for (int c0 = 0; c0 < SG_BK; c0 += CPP) {
-            const int cc = c0 + tid / TPC, r = (tid % TPC) * E;
-            {
-                const int jj = j0 + cc;
-                float v[E];
-                if (jj < J && i0 + r < pitch) {
-                    const unsigned char *src = table + (size_t)el[jj] * (size_t)col_bytes + (size_t)(i0 + r) * (size_t)(16 / E);
-                    widen<DT>(__builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src)), v);
-                } else {
+        for (int ps = 0; ps < PASSES; ++ps) {
+            const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
+            float v[E];
+            widen<DT>(ra[ps], v);
 #pragma unroll
-                    for (int e = 0; e < E; ++e) v[e] = 0.f;
-                }
-#pragma unroll
-                for (int e = 0; e < E; e += 4)
-                    *reinterpret_cast<f32x4 *>(&As[cc][r + e]) = f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]};
-            }
+            for (int e = 0; e < E; e += 4)
+                *reinterpret_cast<f32x4 *>(&As[cc][r + e]) = f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]};
         }
-        // B stage: SG_BK draws x 64 vectors, eight consecutive draws a thread
-        {
-            const int tt = tid >> 2, q = (tid & 3) * 8;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int jj = j0 + q + e;
-                Bs[q + e][tt] = (tt < nx && jj < J) ? cf[(size_t)tt * N + jj] : 0.f;
-            }
-        }
+        for (int e = 0; e < 8; ++e) Bs[bq + e][bt] = rb[e];
         __syncthreads();
+        if (j0 + SG_BK < J) fetch(j0 + SG_BK);
 #pragma unroll
         for (int kk = 0; kk < SG_BK; kk += 4) {
             float fa[2], fb[4];
@@ -164,17 +310,17 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
 }
 
 int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs, uint64_t seed,
-                       int64_t t0, int N, uint32_t *ell, float *coef, uint32_t *dbg_samples, float *dbg_coef,
-                       hipStream_t s) {
-    const int ny = (N + SH_CHUNK - 1) / SH_CHUNK;
-    if (ny > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: J K must stay below 2^26");
-    dim3 grid(batch, ny);
-    if (n <= 2048)
-        hipLaunchKernelGGL(k_shared_coef<1>, grid, dim3(GATHER_THREADS), 0, s, X, n, k, L, signs, seed, t0, N, ell,
-                           coef, dbg_samples, dbg_coef);
-    else
-        hipLaunchKernelGGL(k_shared_coef<2>, grid, dim3(GATHER_THREADS), 0, s, X, n, k, L, signs, seed, t0, N, ell,
-                           coef, dbg_samples, dbg_coef);
+                       int64_t t0, int N, int8_t *digits, int2 *xscale, uint32_t *ell, float *coef,
+                       uint32_t *dbg_samples, float *dbg_coef, hipStream_t s) {
+    const int groups = (batch + ST - 1) / ST;
+    const int nb = (N + 63) / 64;
+    if (nb > 2147483647 / 64 || groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: launch too large");
+    const int n_pad = shared_n_pad(n);
+    if (n <= 2048) hipLaunchKernelGGL(k_x_digits<1>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
+    else hipLaunchKernelGGL(k_x_digits<2>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
+    KD_LAUNCH("k_x_digits");
+    hipLaunchKernelGGL(k_shared_coef, dim3(nb, groups), dim3(256), 0, s, X, n, n_pad, k, L, signs, seed, t0, batch, N,
+                       digits, xscale, ell, coef, dbg_samples, dbg_coef);
     KD_LAUNCH("k_shared_coef");
     return KERDOCK_OK;
 }
