@@ -77,7 +77,7 @@ static int gather_unroll(const kerdock_handle_s *h) {
 
 // workspace layout of the streaming step
 struct Workspace {
-    size_t partial, surv, nsurv, svals, total;
+    size_t partial, surv, nsurv, svals, rows, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -90,6 +90,7 @@ static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, i
     w.surv = off;    off += align256((size_t)batch * s_max * 4);
     w.nsurv = off;   off += align256((size_t)batch * 4);
     w.svals = off;   off += align256((size_t)batch * s_max * 4);
+    w.rows = off;    off += align256(survivor_rows_bytes(batch, h->m, s_max));
     w.total = off;
     return w;
 }
@@ -168,6 +169,7 @@ static int check_apply_args(kerdock_handle h, const float *X, int batch, float e
         return fail(KERDOCK_ERR_INVALID_ARG, "chunk must lie in [0, 1024]");
     if ((p->dbg_samples == nullptr) != (p->dbg_coef == nullptr))
         return fail(KERDOCK_ERR_INVALID_ARG, "dbg_samples and dbg_coef must be given together");
+    if ((int64_t)batch * s_max >= ((int64_t)1 << 31)) return fail(KERDOCK_ERR_INVALID_ARG, "batch s_max must stay below 2^31");
     if (batch == 0) return 1;
     if (!X || !out_idx || !out_val || !out_cnt)
         return fail(KERDOCK_ERR_INVALID_ARG, "NULL input or output pointer");
@@ -194,6 +196,7 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
     float *svals = reinterpret_cast<float *>(ws + lay.svals);
+    int *row_ws = reinterpret_cast<int *>(ws + lay.rows);
 
     // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
     // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
@@ -232,7 +235,7 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
     SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr,
-                svals, surv_vec4(X, h->n)};
+                svals, surv_vec4(X, h->n), h->m, row_ws};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;
@@ -443,6 +446,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     const size_t o_svals = off;   off += align256((size_t)batch * s_max * 4);
     const size_t o_digits = off;  off += align256((size_t)batch * 4 * shared_n_pad(h->n));
     const size_t o_xscale = off;  off += align256((size_t)batch * 8);
+    const size_t o_rows = off;    off += align256(survivor_rows_bytes(batch, h->m, s_max));
     int rc = ensure_workspace(h, off);
     if (rc != KERDOCK_OK) return rc;
     char *ws = reinterpret_cast<char *>(h->ws);
@@ -454,6 +458,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     float *svals = reinterpret_cast<float *>(ws + o_svals);
     int8_t *digits = reinterpret_cast<int8_t *>(ws + o_digits);
     int2 *xscale = reinterpret_cast<int2 *>(ws + o_xscale);
+    int *row_ws = reinterpret_cast<int *>(ws + o_rows);
 
     // kernel_ms: [0] draws + coefficients, [1] matrix product, [2] select,
     // [3] survivors
@@ -470,7 +475,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
     SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, nullptr, nullptr,
-                svals, surv_vec4(X, h->n)};
+                svals, surv_vec4(X, h->n), h->m, row_ws};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;

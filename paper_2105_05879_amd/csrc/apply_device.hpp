@@ -286,7 +286,6 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     const int kb = cid / chunks_per_batch, cj = cid % chunks_per_batch;
     const int jbeg = kb * J + cj * chunk;
     const int cnt = min(chunk, (kb + 1) * J - jbeg);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     // ---------------------------------------------------------- phase 1
     draws_coefs<P>(X + (size_t)t * n, n, k, L, signs, seed, (uint64_t)(t0 + t), 0, jbeg, cnt, s_ell, s_coef);
@@ -582,16 +581,6 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
 }
 
 // ------------------------------------------------------------- survivors --
-// Dot2 (Ogita, Rump, Oishi, "Accurate sum and dot product", SIAM J. Sci.
-// Comput. 2005): error-free products and sums, so the FP32 result is as
-// accurate as if computed in twice the working precision.
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-#pragma clang fp contract(off)
-    s = a + b;
-    const float z = s - a;
-    e = (a - (s - z)) + (b - z);
-}
-
 // Inputs and outputs of the survivor dots and threshold for one handle.
 struct SurvArgs {
     const float *A;
@@ -606,9 +595,22 @@ struct SurvArgs {
     float *dbg_values;        // optional [batch][s_max]
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
     float *vsum2;             // optional [batch]: sum over S of (a_i.x)^2
-    float *svals;             // [batch][s_max] survivor values (split launch)
+    float *svals;             // [batch][s_max] survivor values (split launches)
     int vec4;                 // rows of A and X may be read as 16-byte pieces
+    int m;                    // rows of A (row-merged launch)
+    int *row_ws;              // row-merged launch workspace (survivor_rows_bytes)
 };
+
+// Row-merged survivor step: the (vector, row) pairs of SURV_SBLOCK
+// consecutive vectors are grouped by row, so each row of A is read once per
+// block of vectors and kept in registers while the vectors that selected it
+// are dotted against it; a block's vectors (SURV_SBLOCK n 4 bytes) stay in
+// the L2 of the one XCD that processes the block.
+constexpr int SURV_SBLOCK = 64;
+inline size_t survivor_rows_bytes(int batch, int m, int s_max) {
+    const size_t nblk = ((size_t)batch + SURV_SBLOCK - 1) / SURV_SBLOCK;
+    return (nblk * m + nblk * (m + 1) + (size_t)batch * s_max) * sizeof(int);
+}
 
 // 16-byte pieces are legal when n is a multiple of 4 and X is 16-byte
 // aligned (A is a device allocation of m x n floats).
@@ -619,22 +621,59 @@ inline int surv_vec4(const float *X, int n) {
 constexpr int SURV_THREADS = 256;
 constexpr int SURV_SPLIT_BATCH = 2048;   // below this many vectors use the split form
 
-// a_i.x by one wave: compensated FP32 dot product (Ogita-Rump-Oishi Dot2).
-// Lane l takes elements l, l + 64, ... (or the 16-byte pieces l, l + 64,
-// ... in element order within each piece), then a compensated butterfly.
+// Survivor dots: compensated FP32 dot product (Ogita, Rump, Oishi, "Accurate
+// sum and dot product", SIAM J. Sci. Comput. 2005, Dot2): error-free products
+// (FMA) and sums (TwoSum), so the result is as accurate as if computed in
+// twice the working precision and then rounded.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    const float z = s - a;
+    e = (a - (s - z)) + (b - z);
+}
+
+// one Dot2 step: (p, e) += a b
+__device__ __forceinline__ void dot_step(float &p, float &e, float a, float b) {
+#pragma clang fp contract(off)
+    const float h = a * b;
+    const float rr = fmaf(a, b, -h);
+    float sum, err;
+    two_sum(p, h, sum, err);
+    p = sum;
+    e = e + (err + rr);
+}
+
+// four cascades (one per element position of a 16-byte piece) joined with
+// TwoSum, then a compensated butterfly over the wave; every lane returns the
+// rounded total
+__device__ __forceinline__ float dot_finish(const float (&p)[4], const float (&e)[4]) {
+#pragma clang fp contract(off)
+    float pp = p[0], ee = e[0];
+#pragma unroll
+    for (int c = 1; c < 4; ++c) {
+        float sum, err;
+        two_sum(pp, p[c], sum, err);
+        pp = sum;
+        ee = ee + (e[c] + err);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const float p2 = __shfl_xor(pp, off), e2 = __shfl_xor(ee, off);
+        float sum, err;
+        two_sum(pp, p2, sum, err);
+        pp = sum;
+        ee = ee + e2 + err;
+    }
+    return pp + ee;
+}
+
+// a_i.x by one wave.  Lane l takes the 16-byte pieces l, l + 64, ..., one
+// Dot2 cascade per element position of a piece (or, when rows cannot be read
+// in pieces, elements l, l + 64, ... into one cascade).
 __device__ __forceinline__ float survivor_dot(const float *__restrict__ row, const float *__restrict__ x,
                                               int n, int vec4) {
-#pragma clang fp contract(off)
     const int lane = threadIdx.x & 63;
-    float p = 0.f, e = 0.f;
-    auto step = [&](float a, float b) {
-        const float h = a * b;
-        const float rr = fmaf(a, b, -h);
-        float sum, err;
-        two_sum(p, h, sum, err);
-        p = sum;
-        e = e + (err + rr);
-    };
+    float p[4] = {0.f, 0.f, 0.f, 0.f}, e[4] = {0.f, 0.f, 0.f, 0.f};
     if (vec4) {
         const float4 *__restrict__ r4 = reinterpret_cast<const float4 *>(row);
         const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
@@ -642,23 +681,36 @@ __device__ __forceinline__ float survivor_dot(const float *__restrict__ row, con
 #pragma unroll 4
         for (int q = lane; q < n4; q += 64) {
             const float4 a = r4[q], b = x4[q];
-            step(a.x, b.x);
-            step(a.y, b.y);
-            step(a.z, b.z);
-            step(a.w, b.w);
+            dot_step(p[0], e[0], a.x, b.x);
+            dot_step(p[1], e[1], a.y, b.y);
+            dot_step(p[2], e[2], a.z, b.z);
+            dot_step(p[3], e[3], a.w, b.w);
         }
     } else {
-        for (int q = lane; q < n; q += 64) step(row[q], x[q]);
+        for (int q = lane; q < n; q += 64) dot_step(p[0], e[0], row[q], x[q]);
     }
+    return dot_finish(p, e);
+}
+
+// The same dot (16-byte path) with the row already in registers: rr[i] is
+// the piece lane + 64 i of the row (n <= 4096).
+__device__ __forceinline__ float survivor_dot_regs(const float4 (&rr)[16], const float *__restrict__ x, int n) {
+    const int lane = threadIdx.x & 63;
+    const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
+    const int n4 = n >> 2;
+    float p[4] = {0.f, 0.f, 0.f, 0.f}, e[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const float p2 = __shfl_xor(p, off), e2 = __shfl_xor(e, off);
-        float sum, err;
-        two_sum(p, p2, sum, err);
-        p = sum;
-        e = e + e2 + err;
+    for (int i = 0; i < 16; ++i) {
+        const int q = lane + 64 * i;
+        if (q < n4) {
+            const float4 b = x4[q];
+            dot_step(p[0], e[0], rr[i].x, b.x);
+            dot_step(p[1], e[1], rr[i].y, b.y);
+            dot_step(p[2], e[2], rr[i].z, b.z);
+            dot_step(p[3], e[3], rr[i].w, b.w);
+        }
     }
-    return p + e;
+    return dot_finish(p, e);
 }
 
 // Threshold and compaction of the values of vector t by one wave: rows of S

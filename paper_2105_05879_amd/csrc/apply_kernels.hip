@@ -33,6 +33,89 @@ __global__ __launch_bounds__(SURV_THREADS) void k_survivor_dots(SurvArgs a) {
     survivor_dots_split(a, blockIdx.y, blockIdx.x * (SURV_THREADS / 64) + (threadIdx.x >> 6));
 }
 
+// ---- row-merged survivor step (many vectors): count, scan, scatter, dots
+// row_ws: cnt [nblk][m], off [nblk][m + 1], pairs [batch * s_max]
+__global__ void k_rows_zero(int *__restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// grid (batch), one wave: cnt[blk][row] += 1 for every row of S_t
+__global__ __launch_bounds__(64) void k_rows_count(SurvArgs a) {
+    const int t = blockIdx.x, blk = t / SURV_SBLOCK;
+    if (a.active && !a.active[t]) return;
+    const int ns = min(a.nsurv[t], a.s_max);
+    int *cnt = a.row_ws + (size_t)blk * a.m;
+    for (int s = threadIdx.x; s < ns; s += 64) atomicAdd(&cnt[a.surv[(size_t)t * a.s_max + s]], 1);
+}
+
+// grid (nblk), SELECT_THREADS: off[blk][i] = sum of cnt[blk][< i], i <= m
+__global__ __launch_bounds__(SELECT_THREADS) void k_rows_scan(SurvArgs a, int nblk) {
+    __shared__ int scan_sh[SELECT_THREADS / 64 + 1];
+    const int blk = blockIdx.x, m = a.m;
+    const int *cnt = a.row_ws + (size_t)blk * m;
+    int *off = a.row_ws + (size_t)nblk * m + (size_t)blk * (m + 1);
+    const int per = (m + SELECT_THREADS - 1) / SELECT_THREADS;
+    const int i0 = min(m, (int)threadIdx.x * per), i1 = min(m, i0 + per);
+    int local = 0;
+    for (int i = i0; i < i1; ++i) local += cnt[i];
+    int total;
+    int run = block_exclusive_scan(local, &total, scan_sh);
+    for (int i = i0; i < i1; ++i) {
+        off[i] = run;
+        run += cnt[i];
+    }
+    if (threadIdx.x == 0) off[m] = total;
+}
+
+// grid (batch), one wave: pair index t s_max + s placed in its row's range
+// (cnt counts back down to zero)
+__global__ __launch_bounds__(64) void k_rows_scatter(SurvArgs a, int nblk) {
+    const int t = blockIdx.x, blk = t / SURV_SBLOCK, m = a.m;
+    if (a.active && !a.active[t]) return;
+    const int ns = min(a.nsurv[t], a.s_max);
+    int *cnt = a.row_ws + (size_t)blk * m;
+    const int *off = a.row_ws + (size_t)nblk * m + (size_t)blk * (m + 1);
+    int *pairs = a.row_ws + (size_t)nblk * m + (size_t)nblk * (m + 1) + (size_t)blk * SURV_SBLOCK * a.s_max;
+    for (int s = threadIdx.x; s < ns; s += 64) {
+        const int row = a.surv[(size_t)t * a.s_max + s];
+        const int pos = off[row] + atomicSub(&cnt[row], 1) - 1;
+        pairs[pos] = t * a.s_max + s;
+    }
+}
+
+// grid (8 ceil(nblk / 8) rg), 256 threads, rg = ceil(m / 4): wave = one row
+// of A, in registers, dotted with every vector of the block that selected
+// it.  Workgroups are dealt to the 8 XCDs in turn, so workgroup id = 8 j + x
+// runs on XCD x; XCD x takes blocks x, x + 8, ..., one after another.
+__global__ __launch_bounds__(SURV_THREADS) void k_rows_dots(SurvArgs a, int nblk) {
+    const int m = a.m, lane = threadIdx.x & 63;
+    const int rg = (m + SURV_THREADS / 64 - 1) / (SURV_THREADS / 64);
+    const int xcd = blockIdx.x % 8, jx = blockIdx.x / 8;
+    const int blk = xcd + 8 * (jx / rg);
+    const int row = (jx % rg) * (SURV_THREADS / 64) + (threadIdx.x >> 6);
+    if (blk >= nblk || row >= m) return;
+    const int *off = a.row_ws + (size_t)nblk * m + (size_t)blk * (m + 1);
+    const int beg = off[row], end = off[row + 1];
+    if (beg == end) return;
+    const int *pairs = a.row_ws + (size_t)nblk * m + (size_t)nblk * (m + 1) + (size_t)blk * SURV_SBLOCK * a.s_max;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f *r4 = reinterpret_cast<const v4f *>(a.A + (size_t)row * a.n);
+    const int n4 = a.n >> 2;
+    float4 rr[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = lane + 64 * i;
+        const v4f v = q < n4 ? __builtin_nontemporal_load(r4 + q) : v4f{0.f, 0.f, 0.f, 0.f};
+        rr[i] = make_float4(v.x, v.y, v.z, v.w);
+    }
+    for (int pi = beg; pi < end; ++pi) {
+        const int idx = pairs[pi];
+        const int t = idx / a.s_max;
+        const float v = survivor_dot_regs(rr, a.X + (size_t)t * a.n, a.n);
+        if (lane == 0) a.svals[idx] = v;
+    }
+}
+
 // grid (batch), one wave
 __global__ __launch_bounds__(64) void k_survivor_compact(SurvArgs a) {
     const int t = blockIdx.x;
@@ -174,6 +257,21 @@ int launch_survivors(const SurvArgs &a, int batch, hipStream_t s) {
         const int per = SURV_THREADS / 64;
         hipLaunchKernelGGL(k_survivor_dots, dim3((a.s_max + per - 1) / per, batch), dim3(SURV_THREADS), 0, s, a);
         KD_LAUNCH("k_survivor_dots");
+        hipLaunchKernelGGL(k_survivor_compact, dim3(batch), dim3(64), 0, s, a);
+        KD_LAUNCH("k_survivor_compact");
+        return KERDOCK_OK;
+    }
+    if (a.svals && a.row_ws && a.vec4 && a.n <= 4096) {
+        const int nblk = (batch + SURV_SBLOCK - 1) / SURV_SBLOCK;
+        hipLaunchKernelGGL(k_rows_zero, dim3(256), dim3(256), 0, s, a.row_ws, (size_t)nblk * a.m);
+        hipLaunchKernelGGL(k_rows_count, dim3(batch), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_rows_scan, dim3(nblk), dim3(SELECT_THREADS), 0, s, a, nblk);
+        hipLaunchKernelGGL(k_rows_scatter, dim3(batch), dim3(64), 0, s, a, nblk);
+        const int per = SURV_THREADS / 64;
+        const long long wgs = 8ll * ((nblk + 7) / 8) * ((a.m + per - 1) / per);
+        if (wgs > 2147483647ll) return fail(KERDOCK_ERR_INVALID_ARG, "batch too large for the row-merged survivor grid");
+        hipLaunchKernelGGL(k_rows_dots, dim3((unsigned)wgs), dim3(SURV_THREADS), 0, s, a, nblk);
+        KD_LAUNCH("k_rows_dots");
         hipLaunchKernelGGL(k_survivor_compact, dim3(batch), dim3(64), 0, s, a);
         KD_LAUNCH("k_survivor_compact");
         return KERDOCK_OK;
