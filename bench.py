@@ -348,6 +348,77 @@ def paper_form(kd, torch, np, workloads, args):
     return res
 
 
+def toy_sweep(kd, torch, np, workloads, args):
+    """Section 2.1's toy model at n = 4096: A orthogonal, every entry of Ax
+    N(0,1) with probability p, x normalised, s = 10 p n rows kept, eps =
+    alpha / sqrt(p n).  For p n from 2 to 400 (the model's range is 1 << p n
+    << n / log n), K = 2 and the cheapest J of a doubling grid whose mean
+    recall of supp h_eps(Ax) reaches the target on a calibration batch; both
+    forms (per-vector BF16 gather, shared draws with matrix products) are
+    timed on 4096 vectors against FP32 GEMM and GEMV on the same GPU."""
+    n, B, K, alpha = 4096, 4096, 2, args.alpha
+    J_GRID = [64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
+    w0 = workloads.toy_model(1, 1.0 / n)
+    A = torch.from_numpy(w0.A).cuda()
+    h = kd.kerdock_prepare(A, "bf16")
+    Xd = torch.randn(B, n, device="cuda")
+    base = dense_baselines(torch, A, Xd)
+    del Xd
+    rows = []
+    for pn in args.sweep_pn:
+        p = pn / n
+        eps = alpha / np.sqrt(pn)
+        s_max = int(min(n, np.ceil(10 * pn)))
+        w = workloads.toy_model(B, p)
+        wc = workloads.toy_model(256, p, seed_X=workloads.SEED_X + 9)
+        A64 = w.A.astype(np.float64)
+        sup, Ax = eps_supports(A64, w.X.astype(np.float64), eps)
+        sup_c, _ = eps_supports(A64, wc.X.astype(np.float64), eps)
+        X = torch.from_numpy(w.X).cuda()
+        Xc = torch.from_numpy(wc.X).cuda()
+        J, rc = J_GRID[-1], float("nan")
+        for Jt in J_GRID:
+            idx, val, cnt = kd.kerdock_sparse_apply(h, Xc, eps, s_max, Jt, K, args.seed)
+            torch.cuda.synchronize()
+            r = float(np.mean(recall_of(idx.cpu().numpy(), cnt.cpu().numpy(), sup_c)))
+            if r >= args.recall:
+                J, rc = Jt, r
+                break
+        kd.kerdock_reserve(h, B, J, K, s_max)
+        res = {"pn": pn, "p": p, "eps": eps, "s_max": s_max, "J": J, "K": K, "calib_recall": rc,
+               "eps_support_mean": float(np.mean([len(q) for q in sup])),
+               # the model's estimate quality |h_eps(Ax) - Ax|^2
+               "threshold_error_mean": float(np.mean(np.sum(np.where(np.abs(Ax) >= eps, 0.0, Ax) ** 2, axis=1)))}
+        for form, fn in (("per_vector", kd.kerdock_sparse_apply), ("shared", kd.kerdock_sparse_apply_shared)):
+            if form == "shared" and J * K > n:
+                # its matrix product would cost more flops than the dense one
+                res[form] = None
+                continue
+            fn(h, X, eps, s_max, J, K, args.seed, t0=0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for sidx in range(args.steps):
+                out = fn(h, X, eps, s_max, J, K, args.seed, t0=(sidx + 1) * B)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / args.steps
+            idx, val, cnt = (o.cpu().numpy() for o in out)
+            res[form] = {"x_per_s": B / el, "recall_mean": float(np.mean(recall_of(idx, cnt, sup))),
+                         "vs_gemm": B / el / base["dense_gemm_f32_x_per_s"],
+                         "vs_gemv": B / el / base["dense_gemv_f32_x_per_s"]}
+        sh = res["shared"]
+        log("toy p n = %g: eps %.4f s_max %d J %d, per-vector %.0f x/s (recall %.4f), shared %s (GEMM %.0f, "
+            "GEMV %.0f)" % (pn, eps, s_max, J, res["per_vector"]["x_per_s"], res["per_vector"]["recall_mean"],
+                            "%.0f x/s (recall %.4f)" % (sh["x_per_s"], sh["recall_mean"]) if sh else "skipped",
+                            base["dense_gemm_f32_x_per_s"], base["dense_gemv_f32_x_per_s"]))
+        rows.append(res)
+        del X, Xc
+        torch.cuda.empty_cache()
+    h.destroy()
+    return {"workload": "toy model n=4096 Haar A, alpha=%g, K=2, BF16 table, 4096 x" % alpha,
+            "dense_gemm_f32_x_per_s": base["dense_gemm_f32_x_per_s"],
+            "dense_gemv_f32_x_per_s": base["dense_gemv_f32_x_per_s"], "rows": rows}
+
+
 def learned_form(kd, torch, np, workloads, args):
     """n = 1024 structured dictionary, supports from a pool of 512 size-16
     patterns: the MLP proposer (1024 -> 512 -> 512 -> 1024) is trained on
@@ -526,6 +597,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the numerical-section regime")
+    ap.add_argument("--sweep", action="store_true",
+                    help="run only the toy-model regime sweep (its own JSON line)")
+    ap.add_argument("--sweep-pn", dest="sweep_pn", type=float, nargs="+",
+                    default=[2, 5, 10, 20, 50, 100, 200, 400])
+    ap.add_argument("--alpha", type=float, default=0.5)
     ap.add_argument("--learned-train", type=int, default=1 << 18)
     ap.add_argument("--learned-test", type=int, default=1 << 14)
     ap.add_argument("--learned-epochs", type=int, default=8)
@@ -547,6 +623,12 @@ def main():
 
     kd.lib()
     torch.cuda.set_device(0)
+    if args.sweep:
+        r = toy_sweep(kd, torch, np, workloads, args)
+        print(json.dumps({"metric": "toy-model regime sweep (Section 2.1): thresholded-Ax/s vs dense",
+                          "unit": "thresholded-Ax/s", "n_gpus": 1, "steps": args.steps, "data": "synthetic",
+                          "sweep": r}), flush=True)
+        return
     if args.copy_probe:
         src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -210,3 +210,20 @@ def near_sparse(batch=400, m=768, n=1000, s=8, delta=0.02, seed_A=SEED_A + 7, se
     w = Workload("near_sparse", A, X, 0.85 * mag_min, sup, s)
     w.delta = float(delta)
     return w
+
+
+def toy_model(batch, p, n=4096, seed_A=SEED_A + 6, seed_X=SEED_X + 8):
+    """Section 2.1's model: A orthogonal (Haar, the paper-regime matrix for
+    n = 4096), every entry of y = Ax independently N(0, 1) with probability p
+    and 0 otherwise; x = A^T y / |y| so that A x is the unit vector y / |y|.
+    eps is not set (the sweep scales it as alpha / sqrt(p n)); supports are
+    the nonzero rows of y."""
+    A = haar_orthogonal(n, np.random.default_rng(seed_A))
+    rx = np.random.default_rng(seed_X + int(round(p * 1e6)))
+    Y = np.where(rx.random((batch, n)) < p, rx.standard_normal((batch, n)), 0.0)
+    empty = np.linalg.norm(Y, axis=1) == 0
+    Y[empty, 0] = 1.0                        # keep every row a unit vector
+    Y /= np.linalg.norm(Y, axis=1, keepdims=True)
+    X = Y @ A
+    sup = [np.flatnonzero(y) for y in Y]
+    return Workload("toy p=%g" % p, A, X, 0.0, sup, int(round(p * n)))
