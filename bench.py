@@ -111,6 +111,29 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
     col_bytes = info.m * BYTES[dt]
     gather_bytes = B * N * col_bytes
     gbps = gather_bytes / (kern[1] * 1e-3) / 1e9
+    shared = None
+    if args.shared:
+        # the same (J, K) with draws shared by groups of 64 x (matrix-product form)
+        kd.kerdock_sparse_apply_shared(h, X, args.eps, args.s_max, J, K, args.seed, out=out)
+        torch.cuda.synchronize()
+        sk = np.zeros(4)
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            kd.kerdock_sparse_apply_shared(h, X, args.eps, args.s_max, J, K, args.seed, t0=(s + 1) * B // 64,
+                                           out=out, kernel_ms=ms)
+            sk += np.array(ms[:4])
+        torch.cuda.synchronize()
+        sel = time.perf_counter() - t0
+        sk /= args.steps
+        sidx, _, scnt = (o.cpu().numpy() for o in out)
+        srec = recall_of(sidx, scnt, supports)
+        shared = {"x_per_s": B * args.steps / sel, "ms_per_step": sel / args.steps * 1e3,
+                  "recall_mean": float(np.mean(srec)), "recall_min": float(np.min(srec)),
+                  "kernel_ms": {"coef": sk[0], "gemm": sk[1], "select": sk[2], "survivors": sk[3]},
+                  "gemm_TFLOPs": 2.0 * info.m * N * B / (sk[1] * 1e-3) / 1e12}
+        log("%s shared draws: %.1f x/s (coef %.3f ms, gemm %.3f ms = %.1f TFLOP/s, select %.3f, survivors %.3f)"
+            "  recall %.4f (min %.3f)" % (dt, shared["x_per_s"], sk[0], sk[1], shared["gemm_TFLOPs"], sk[2], sk[3],
+                                          shared["recall_mean"], shared["recall_min"]))
     h.destroy()
     torch.cuda.empty_cache()
     r = {
@@ -119,7 +142,7 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
         "max_abs_err_vs_fp64": err, "prepare_s": prep, "table_GB": info.table_bytes / 1e9,
         "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
         "gather_GBps": gbps, "gather_frac_hbm": gbps / HBM_PEAK_GBPS,
-        "gather_bytes_per_launch": gather_bytes,
+        "gather_bytes_per_launch": gather_bytes, "shared_draws": shared,
     }
     log("%s: J=%d K=%d  %.1f x/s  %.2f ms/step  gather %.3f ms = %.0f GB/s (%.1f%%)  recall %.4f (min %.3f)  max err %.2g"
         % (dt, J, K, r["x_per_s"], r["ms_per_step"], kern[1], gbps, 100 * gbps / HBM_PEAK_GBPS,
@@ -597,6 +620,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the numerical-section regime")
+    ap.add_argument("--no-shared", dest="shared", action="store_false",
+                    help="skip the shared-draw variant of each table type")
     ap.add_argument("--sweep", action="store_true",
                     help="run only the toy-model regime sweep (its own JSON line)")
     ap.add_argument("--sweep-pn", dest="sweep_pn", type=float, nargs="+",

@@ -34,6 +34,7 @@ int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const
                        int64_t t0, int N, int8_t *digits, int2 *xscale, uint32_t *ell, float *coef,
                        uint32_t *dbg_samples, float *dbg_coef, hipStream_t s);
 int shared_n_pad(int n);
+int shared_splits(int J);
 int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch, int J, int K, const uint32_t *ell,
                        const float *coef, float *partial, hipStream_t s);
 
@@ -438,7 +439,8 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const size_t groups = ((size_t)batch + KERDOCK_SHARED_TILE - 1) / KERDOCK_SHARED_TILE;
     size_t off = 0;
-    const size_t o_partial = off; off += align256((size_t)batch * K * h->pitch * 4);
+    const int splits = shared_splits(J);
+    const size_t o_partial = off; off += align256((size_t)batch * K * splits * h->pitch * 4);
     const size_t o_coef = off;    off += align256(groups * KERDOCK_SHARED_TILE * N * 4);
     const size_t o_ell = off;     off += align256(groups * N * 4);
     const size_t o_surv = off;    off += align256((size_t)batch * s_max * 4);
@@ -471,7 +473,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
     if (rc == KERDOCK_OK) rc = launch_shared_gemm(h->dtype, h->table, h->pitch, batch, J, K, ell, coef, partial, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
-    SelArgs sa{partial, h->m, h->pitch, K, 1, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, nullptr};
+    SelArgs sa{partial, h->m, h->pitch, K, splits, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, nullptr};
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
     SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, nullptr, nullptr,

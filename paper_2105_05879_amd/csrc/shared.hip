@@ -119,29 +119,38 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
         for (int c = 0; c < 4; ++c) acc[b][c] = i32x4{0, 0, 0, 0};
     __syncthreads();
 
+    // the digits and sign word of step q0 + 32 are loaded while the MFMAs of
+    // step q0 run
+    const int tv_s = tid >> 2, b_s = tid & 3;
+    uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
+    uint32_t wd = 0u;
+    auto fetch = [&](int q0) {
+        if (tv_s < nx) {
+            const uint4 *src =
+                reinterpret_cast<const uint4 *>(digits + ((size_t)(g * ST + tv_s) * 4 + b_s) * n_pad + q0);
+            lo = src[0];
+            hi = src[1];
+        }
+        const int q = q0 + kq;
+        // coordinates past d (only when n_pad > d) meet zero digits
+        wd = (kerdock_row && (q >> 5) < words) ? signs[(size_t)bb * words + (q >> 5)] : 0u;
+    };
+    fetch(0);
     for (int q0 = 0; q0 < n_pad; q0 += 32) {
-        {   // digits of the group's vectors: 32 bytes per (vector, digit)
-            const int tv = tid >> 2, b = tid & 3;
-            uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
-            if (tv < nx) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(
-                    digits + ((size_t)(g * ST + tv) * 4 + b) * n_pad + q0);
-                lo = src[0];
-                hi = src[1];
-            }
-            uint4 *dst = reinterpret_cast<uint4 *>(&Bs[b][tv][0]);
+        {
+            uint4 *dst = reinterpret_cast<uint4 *>(&Bs[b_s][tv_s][0]);
             dst[0] = lo;
             dst[1] = hi;
         }
         long a = 0;
         if (kerdock_row) {
             const int q = q0 + kq;
-            const uint32_t wd = signs[(size_t)bb * words + (q >> 5)];
             const uint32_t par = __popc((uint32_t)q & ww) & 1u;
             const uint32_t m8 = ((wd >> (q & 31)) & 0xFFu) ^ w8 ^ (par ? 0xFFu : 0u);
             a = (long)lut[m8];
         }
         __syncthreads();
+        if (q0 + 32 < n_pad) fetch(q0 + 32);
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -215,13 +224,19 @@ __device__ __forceinline__ void widen(const u32x4 raw, float *v) {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// k_shared_gemm: grid (ceil(pitch / 128), K, groups), 256 threads.  Rows
-// i0 .. i0 + 127 of Y_k for the (up to) 64 vectors of group g:
-// partial[t][k][i] = sum_{j < J} T[ell[g][k J + j]][i] coef[g][t][k J + j].
-// Wave w owns rows i0 + 32 w .. + 31, all 64 vectors: 2 x 4 MFMA blocks.
+// Draws of a batch are split into `splits` consecutive slices (a function of
+// J alone, so results never depend on the batch size), each summed by its
+// own workgroups; the slices are added in order with the batch mean.
+int shared_splits(int J) { return J / 2048 < 1 ? 1 : J / 2048 > 16 ? 16 : J / 2048; }
+
+// k_shared_gemm: grid (ceil(pitch / 128), K splits, groups), 256 threads.
+// Rows i0 .. i0 + 127 of slice sp of Y_k for the (up to) 64 vectors of
+// group g: partial[t][k][sp][i] = sum_{j in slice} T[ell[g][k J + j]][i]
+// coef[t][k J + j].  Wave w owns rows i0 + 32 w .. + 31, all 64 vectors:
+// 2 x 4 MFMA blocks.
 template <int DT>
 __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__restrict__ table, int col_bytes, int pitch,
-                                                     int batch, int J, int K, int N,
+                                                     int batch, int J, int K, int N, int splits,
                                                      const uint32_t *__restrict__ ell,
                                                      const float *__restrict__ coef,
                                                      float *__restrict__ partial) {
@@ -231,11 +246,13 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
     static_assert(SG_BK % CPP == 0, "whole passes");
     __shared__ float As[SG_BK][SG_BM + 16];   // [draw][row]; row stride = 16 mod 64 banks
     __shared__ float Bs[SG_BK][ST + 16];      // [draw][vector]
-    const int g = blockIdx.z, kb = blockIdx.y, i0 = blockIdx.x * SG_BM;
+    const int g = blockIdx.z, kb = blockIdx.y / splits, sp = blockIdx.y % splits, i0 = blockIdx.x * SG_BM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nx = min(ST, batch - g * ST);
-    const uint32_t *__restrict__ el = ell + (size_t)g * N + (size_t)kb * J;
-    const float *__restrict__ cf = coef + (size_t)g * ST * N + (size_t)kb * J;
+    const int js = (int)(((long long)J * sp) / splits);
+    const int Jl = (int)(((long long)J * (sp + 1)) / splits) - js;     // draws of this slice
+    const uint32_t *__restrict__ el = ell + (size_t)g * N + (size_t)kb * J + js;
+    const float *__restrict__ cf = coef + (size_t)g * ST * N + (size_t)kb * J + js;
     const int wi = wave * 32;
     f32x4 acc[2][4];
 #pragma unroll
@@ -255,7 +272,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
             const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
             const int jj = j0 + cc;
             ra[ps] = u32x4{0u, 0u, 0u, 0u};
-            if (jj < J && i0 + r < pitch) {
+            if (jj < Jl && i0 + r < pitch) {
                 const unsigned char *src =
                     table + (size_t)el[jj] * (size_t)col_bytes + (size_t)(i0 + r) * (size_t)(16 / E);
                 ra[ps] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src));
@@ -264,11 +281,11 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int jj = j0 + bq + e;
-            rb[e] = (bt < nx && jj < J) ? cf[(size_t)bt * N + jj] : 0.f;
+            rb[e] = (bt < nx && jj < Jl) ? cf[(size_t)bt * N + jj] : 0.f;
         }
     };
     fetch(0);
-    for (int j0 = 0; j0 < J; j0 += SG_BK) {
+    for (int j0 = 0; j0 < Jl; j0 += SG_BK) {
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) {
             const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
@@ -281,7 +298,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
 #pragma unroll
         for (int e = 0; e < 8; ++e) Bs[bq + e][bt] = rb[e];
         __syncthreads();
-        if (j0 + SG_BK < J) fetch(j0 + SG_BK);
+        if (j0 + SG_BK < Jl) fetch(j0 + SG_BK);
 #pragma unroll
         for (int kk = 0; kk < SG_BK; kk += 4) {
             float fa[2], fb[4];
@@ -305,7 +322,8 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
             const int row = i0 + wi + a * 16 + 4 * (lane >> 4);
             const int tt = b * 16 + (lane & 15);
             if (tt < nx && row < pitch)
-                *reinterpret_cast<f32x4 *>(partial + ((size_t)(g * ST + tt) * K + kb) * pitch + row) = acc[a][b];
+                *reinterpret_cast<f32x4 *>(partial + (((size_t)(g * ST + tt) * K + kb) * splits + sp) * pitch + row) =
+                    acc[a][b];
         }
 }
 
@@ -314,7 +332,7 @@ int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const
                        uint32_t *dbg_samples, float *dbg_coef, hipStream_t s) {
     const int groups = (batch + ST - 1) / ST;
     const int nb = (N + 63) / 64;
-    if (nb > 2147483647 / 64 || groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: launch too large");
+    if (groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: launch too large");
     const int n_pad = shared_n_pad(n);
     if (n <= 2048) hipLaunchKernelGGL(k_x_digits<1>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
     else hipLaunchKernelGGL(k_x_digits<2>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
@@ -329,20 +347,21 @@ int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch
                        const float *coef, float *partial, hipStream_t s) {
     const int groups = (batch + ST - 1) / ST;
     if (groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: batch too large");
-    dim3 grid((pitch + SG_BM - 1) / SG_BM, K, groups);
+    const int splits = shared_splits(J);
+    dim3 grid((pitch + SG_BM - 1) / SG_BM, K * splits, groups);
     const unsigned char *tb = reinterpret_cast<const unsigned char *>(table);
     const int cb = pitch * (int)dtype_bytes(dt), N = J * K;
     switch (dt) {
     case KERDOCK_F32:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_F32>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, ell,
+        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_F32>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
                            coef, partial);
         break;
     case KERDOCK_BF16:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_BF16>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, ell,
+        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_BF16>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
                            coef, partial);
         break;
     case KERDOCK_FP8E4M3:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_FP8E4M3>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, ell,
+        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_FP8E4M3>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
                            coef, partial);
         break;
     }
