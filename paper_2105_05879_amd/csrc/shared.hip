@@ -17,8 +17,8 @@
 
 namespace kd {
 
-// coordinates of the digit rows: n rounded up to a multiple of 32
-int shared_n_pad(int n) { return (n + 31) / 32 * 32; }
+// coordinates of the digit rows: n rounded up to a multiple of 64
+int shared_n_pad(int n) { return (n + 63) / 64 * 64; }
 
 constexpr int ST = KERDOCK_SHARED_TILE;       // vectors per draw group
 constexpr int SG_BM = 128;                    // table rows per GEMM workgroup
@@ -31,7 +31,7 @@ constexpr int SG_BK = 32;                     // draws per LDS stage
 // the fixed point of the per-vector form, x_int = rint(x 2^E2) with
 // sum |x_int| <= 2^30, each x_int is split into four balanced base-256 digits
 // in [-128, 127], and C is accumulated digit by digit on the int8 matrix cores
-// (16 x 16 x 32 MFMA, int32 accumulators): every step is integer arithmetic,
+// (16 x 16 x 64 MFMA, int32 accumulators): every step is integer arithmetic,
 // so c = (sum_b 256^b C_b) 2^-E2 equals the per-vector form's exact signed sum.
 // Identity draws (basis d/2) give sqrt(d) x[w] directly.
 
@@ -74,12 +74,14 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// k_shared_coef: grid (ceil(N / 64), groups), 256 threads.  Wave w takes
+// k_shared_coef: grid (ceil(N / 64), groups), 256 threads; coef[g][j][t mod
+// 64] (the 64 vectors of a draw contiguous).  Wave w takes
 // draws j0 + 16 w .. + 15 of group g (the 16 rows of its MFMA blocks) against
 // the group's 64 vectors (4 column blocks) and 4 digits: 16 accumulators.
-// Per step of 32 coordinates the digits of the 64 vectors go through LDS;
+// Per step of 64 coordinates the digits of the 64 vectors go through LDS;
 // the sign rows are made in registers from the sign bitmaps and the Walsh
-// pattern of w, eight coordinates (one 64-bit operand) per lane.
+// pattern of w, sixteen coordinates (one 128-bit operand) per lane; A and B
+// give every lane the same 16 consecutive coordinates of the step.
 __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
                                                      const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
                                                      int batch, int N, const int8_t *__restrict__ digits,
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                                      float *__restrict__ coef, uint32_t *__restrict__ dbg_samples,
                                                      float *__restrict__ dbg_coef) {
     __shared__ uint64_t lut[256];                   // 8 sign bits -> 8 bytes of +-1
-    __shared__ __align__(16) int8_t Bs[4][ST][32];  // [digit][vector][coordinate]
+    __shared__ __align__(16) int8_t Bs[4][ST][64];  // [digit][vector][coordinate]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.y, nx = min(ST, batch - g * ST);
     const int d = 1 << k, words = d >= 32 ? d / 32 : 1;
@@ -109,8 +111,9 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
     }
     const uint32_t bb = my_l >> k, ww = my_l & (uint32_t)(d - 1);
     const bool kerdock_row = j < N && (int)bb < d / 2;
-    const uint32_t w8 = (ww & 1u ? 0xAAu : 0u) ^ (ww & 2u ? 0xCCu : 0u) ^ (ww & 4u ? 0xF0u : 0u);
-    const int kq = (lane >> 4) * 8;                  // this lane's 8 coordinates within a step
+    const uint32_t w16 = (ww & 1u ? 0xAAAAu : 0u) ^ (ww & 2u ? 0xCCCCu : 0u) ^ (ww & 4u ? 0xF0F0u : 0u) ^
+                         (ww & 8u ? 0xFF00u : 0u);
+    const int kq = (lane >> 4) * 16;                 // this lane's 16 coordinates within a step
 
     i32x4 acc[4][4];
 #pragma unroll
@@ -119,44 +122,46 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
         for (int c = 0; c < 4; ++c) acc[b][c] = i32x4{0, 0, 0, 0};
     __syncthreads();
 
-    // the digits and sign word of step q0 + 32 are loaded while the MFMAs of
+    // the digits and sign word of step q0 + 64 are loaded while the MFMAs of
     // step q0 run
     const int tv_s = tid >> 2, b_s = tid & 3;
-    uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
+    uint4 dg[4] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
+                   make_uint4(0u, 0u, 0u, 0u)};
     uint32_t wd = 0u;
     auto fetch = [&](int q0) {
         if (tv_s < nx) {
             const uint4 *src =
                 reinterpret_cast<const uint4 *>(digits + ((size_t)(g * ST + tv_s) * 4 + b_s) * n_pad + q0);
-            lo = src[0];
-            hi = src[1];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dg[u] = src[u];
         }
         const int q = q0 + kq;
         // coordinates past d (only when n_pad > d) meet zero digits
         wd = (kerdock_row && (q >> 5) < words) ? signs[(size_t)bb * words + (q >> 5)] : 0u;
     };
     fetch(0);
-    for (int q0 = 0; q0 < n_pad; q0 += 32) {
+    for (int q0 = 0; q0 < n_pad; q0 += 64) {
         {
             uint4 *dst = reinterpret_cast<uint4 *>(&Bs[b_s][tv_s][0]);
-            dst[0] = lo;
-            dst[1] = hi;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = dg[u];
         }
-        long a = 0;
+        i32x4 a = i32x4{0, 0, 0, 0};
         if (kerdock_row) {
             const int q = q0 + kq;
             const uint32_t par = __popc((uint32_t)q & ww) & 1u;
-            const uint32_t m8 = ((wd >> (q & 31)) & 0xFFu) ^ w8 ^ (par ? 0xFFu : 0u);
-            a = (long)lut[m8];
+            const uint32_t m16 = ((wd >> (q & 31)) & 0xFFFFu) ^ w16 ^ (par ? 0xFFFFu : 0u);
+            const uint64_t lo8 = lut[m16 & 0xFFu], hi8 = lut[m16 >> 8];
+            a = i32x4{(int)(uint32_t)lo8, (int)(uint32_t)(lo8 >> 32), (int)(uint32_t)hi8, (int)(uint32_t)(hi8 >> 32)};
         }
         __syncthreads();
-        if (q0 + 32 < n_pad) fetch(q0 + 32);
+        if (q0 + 64 < n_pad) fetch(q0 + 64);
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const long bop = *reinterpret_cast<const long *>(&Bs[b][c * 16 + row][kq]);
-                acc[b][c] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a, bop, acc[b][c], 0, 0, 0);
+                const i32x4 bop = *reinterpret_cast<const i32x4 *>(&Bs[b][c * 16 + row][kq]);
+                acc[b][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bop, acc[b][c], 0, 0, 0);
             }
         __syncthreads();
     }
@@ -186,7 +191,7 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                     ((int64_t)acc[2][c][v] << 16) + ((int64_t)acc[3][c][v] << 24);
                 cf = sc.y ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
             }
-            coef[(size_t)t * N + jr] = cf;
+            coef[((size_t)g * N + jr) * ST + tv] = cf;
             if (tv == 0) ell[(size_t)g * N + jr] = l_r;
             if (dbg_samples) {
                 dbg_samples[(size_t)t * N + jr] = l_r;
@@ -232,7 +237,7 @@ int shared_splits(int J) { return J / 2048 < 1 ? 1 : J / 2048 > 16 ? 16 : J / 20
 // k_shared_gemm: grid (ceil(pitch / 128), K splits, groups), 256 threads.
 // Rows i0 .. i0 + 127 of slice sp of Y_k for the (up to) 64 vectors of
 // group g: partial[t][k][sp][i] = sum_{j in slice} T[ell[g][k J + j]][i]
-// coef[t][k J + j].  Wave w owns rows i0 + 32 w .. + 31, all 64 vectors:
+// coef[g][k J + j][t mod 64].  Wave w owns rows i0 + 32 w .. + 31, all 64 vectors:
 // 2 x 4 MFMA blocks.
 template <int DT>
 __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__restrict__ table, int col_bytes, int pitch,
@@ -252,7 +257,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
     const int js = (int)(((long long)J * sp) / splits);
     const int Jl = (int)(((long long)J * (sp + 1)) / splits) - js;     // draws of this slice
     const uint32_t *__restrict__ el = ell + (size_t)g * N + (size_t)kb * J + js;
-    const float *__restrict__ cf = coef + (size_t)g * ST * N + (size_t)kb * J + js;
+    const float *__restrict__ cf = coef + ((size_t)g * N + (size_t)kb * J + js) * ST;
     const int wi = wave * 32;
     f32x4 acc[2][4];
 #pragma unroll
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
     constexpr int PASSES = SG_BK / CPP;
     u32x4 ra[PASSES];
     float rb[8];
-    const int bt = tid >> 2, bq = (tid & 3) * 8;
+    const int bj = tid >> 3, bv = (tid & 7) * 8;     // B stage: draw bj, vectors bv .. bv + 7
     auto fetch = [&](int j0) {
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) {
@@ -278,10 +283,10 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
                 ra[ps] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src));
             }
         }
+        {
+            const int jj = j0 + bj;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int jj = j0 + bq + e;
-            rb[e] = (bt < nx && jj < Jl) ? cf[(size_t)bt * N + jj] : 0.f;
+            for (int e = 0; e < 8; ++e) rb[e] = (jj < Jl && bv + e < nx) ? cf[(size_t)jj * ST + bv + e] : 0.f;
         }
     };
     fetch(0);
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
                 *reinterpret_cast<f32x4 *>(&As[cc][r + e]) = f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]};
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[bq + e][bt] = rb[e];
+        for (int e = 0; e < 8; ++e) Bs[bj][bv + e] = rb[e];
         __syncthreads();
         if (j0 + SG_BK < Jl) fetch(j0 + SG_BK);
 #pragma unroll
