@@ -129,7 +129,9 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
  *            padded with -1.
  *   out_val  device [batch][s_max] FP32: (Ax)_i for the kept rows, computed
  *            exactly from FP32 A and x (compensated dot product), 0 padded.
- *   out_cnt  device [batch] int32: number of kept rows.
+ *   out_cnt  device [batch] int32: number of kept rows, or -1 when some
+ *            a_i.x with i in S is not finite (an inf or NaN in x or in a
+ *            selected row of A); that vector's rows are then all padding.
  * For every row x: draws l_j (j < N) uniformly from [L]; forms
  * y_j = T[l_j] (s_{l_j}^T x); averages each batch of J draws; takes the
  * entrywise median of the K means (the mean of the two middle values for

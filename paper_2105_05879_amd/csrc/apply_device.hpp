@@ -8,8 +8,11 @@
 //   select_vec     batch means, entrywise median over the K batches, and the
 //                  s_max rows of largest |mu| (ties: smaller index) by an
 //                  LDS radix select, compacted in ascending row order;
-//   survivors_vec  exact a_i.x on the selected rows (compensated FP32 dot
-//                  product, Ogita-Rump-Oishi Dot2) and the eps threshold.
+//   survivors_*    exact a_i.x on the selected rows (compensated FP32 dot
+//                  product, Ogita-Rump-Oishi Dot2) and the eps threshold:
+//                  one workgroup per vector, one wave per row of S (small
+//                  batches), or the rows of S of a block of vectors merged
+//                  so each row of A is read once per block (large batches).
 #pragma once
 
 #include "common.hpp"
@@ -721,10 +724,18 @@ __device__ __forceinline__ void survivors_compact(const SurvArgs &a, int t, cons
     const int lane = threadIdx.x & 63;
     const int s_max = a.s_max;
     const int ns = min(a.nsurv[t], s_max);
+    // a non-finite survivor value (inf or NaN in x or in a selected row of
+    // A) marks the whole vector: count -1, rows all padding
+    bool bad = false;
+    for (int s0 = 0; s0 < ns; s0 += 64) {
+        const int s = s0 + lane;
+        bad = bad || (s < ns && !isfinite(vals[s]));
+    }
+    const bool invalid = __ballot(bad) != 0;
     int base = 0;
     for (int s0 = 0; s0 < s_max; s0 += 64) {
         const int s = s0 + lane;
-        const bool keep = s < ns && fabsf(vals[s]) >= a.eps;
+        const bool keep = !invalid && s < ns && fabsf(vals[s]) >= a.eps;
         const uint64_t mask = __ballot(keep);
         const int pos = base + __popcll(mask & ((1ull << lane) - 1ull));
         if (keep) {
@@ -746,7 +757,7 @@ __device__ __forceinline__ void survivors_compact(const SurvArgs &a, int t, cons
         for (int off = 32; off > 0; off >>= 1) e2 += __shfl_xor(e2, off);
         if (lane == 0) a.vsum2[t] = e2;
     }
-    if (lane == 0) a.out_cnt[t] = base;
+    if (lane == 0) a.out_cnt[t] = invalid ? -1 : base;
 }
 
 // Whole survivor step of vector t in one workgroup (shared memory:

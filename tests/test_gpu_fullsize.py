@@ -80,3 +80,33 @@ def test_fullsize(orc, wl, dtype):
         mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
         dmu = np.abs(g["mu"][t][rows] - mu_o)
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_basis_sums_reproduce_Ax(orc, wl, dtype):
+    """One full basis reproduces Ax: the d design vectors of a basis are sqrt(d)
+    times an orthonormal basis, so (1/d) sum_w T[b d + w] (s_{b d + w}^T x) = Ax
+    for every b.  Checked on the whole n = 2048 table of several bases (the
+    plain Hadamard basis, Kerdock bases, the identity block) with exact
+    coefficients from the oracle's design vectors; the bound is the table's
+    own rounding (FWHT in FP32, then the stored type)."""
+    kd = need_gpu()
+    w, A64, X64 = wl
+    h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
+    info = h.info
+    d, n, k = info.d, info.n, info.k
+    x = X64[0]
+    Ax = A64 @ x
+    l1 = np.abs(A64).sum(1)
+    for b in (0, 1, 1000, d // 2 - 1, d // 2):
+        ells = torch.arange(b * d, (b + 1) * d, dtype=torch.int32, device="cuda")
+        T = kd.kerdock_read_columns(h, ells).double().cpu().numpy()          # [d][m]
+        S = np.stack([orc.design_vector(n, k, l) for l in range(b * d, (b + 1) * d)])
+        c = S @ x
+        est = (c @ T) / d
+        ent = (k + 1) * U32 * l1[None, :] * np.ones_like(T)                  # FP32 FWHT rounding
+        if dtype == "bf16":
+            ent = ent + 2.0 ** -8 * (np.abs(T) + ent)                        # one bf16 rounding
+        tol = (np.abs(c) @ ent) / d + 64 * U32 * (np.abs(c) @ np.abs(T)) / d
+        assert np.all(np.abs(est - Ax) <= tol), (b, float(np.max(np.abs(est - Ax) - tol)))
+    h.destroy()

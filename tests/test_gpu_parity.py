@@ -285,6 +285,26 @@ def test_errors(orc):
     h.destroy()
 
 
+def test_non_finite_input_is_flagged(orc):
+    """An inf or NaN in x makes the survivor values non-finite: count -1 and
+    all-padding rows for that vector, the other vectors unaffected."""
+    kd = need_gpu()
+    A = rand_A(64, 64, 7)
+    Xn = unit_rows(4, 64, 8)
+    Xn[1, 5] = np.nan
+    Xn[2, 9] = np.inf
+    h = prepare(kd, A, "f32")
+    idx, val, cnt = kd.kerdock_sparse_apply(h, torch.from_numpy(Xn).cuda(), 0.05, 8, 40, 2, 11, t0=0)
+    torch.cuda.synchronize()
+    assert cnt[1].item() == -1 and cnt[2].item() == -1
+    assert torch.all(idx[1:3] == -1) and torch.all(val[1:3] == 0)
+    for t in (0, 3):
+        ref = kd.kerdock_sparse_apply(h, torch.from_numpy(Xn[t:t + 1]).cuda(), 0.05, 8, 40, 2, 11, t0=t)
+        assert torch.equal(ref[0][0], idx[t]) and torch.equal(ref[1][0], val[t]) and ref[2][0].item() == cnt[t].item()
+        assert cnt[t].item() >= 0
+    h.destroy()
+
+
 def test_zero_matrix(orc):
     kd = need_gpu()
     h = prepare(kd, np.zeros((40, 40), dtype=np.float32), "fp8")
