@@ -57,7 +57,7 @@ def calibrate(kd, h, Xc, supports, eps, s_max, target, seed):
     """Cheapest (J, K) (fewest draws N = J K) with mean recall >= target."""
     for N in N_GRID:
         best = None
-        for K in (1, 2, 3):
+        for K in (1, 2, 3, 5):
             J = N // K
             idx, val, cnt = kd.kerdock_sparse_apply(h, Xc, eps, s_max, J, K, seed, t0=1 << 40)
             rec = recall_of(idx.cpu().numpy(), cnt.cpu().numpy(), supports)
@@ -164,7 +164,7 @@ def calibrate_planted(kd, h, Xc, sup_c, eps, s_max, target, seed):
     best = None
     for N in PLANTED_GRID:
         best = None
-        for K in (1, 2, 3):
+        for K in (1, 2, 3, 5):
             J = max(1, N // K)
             out = kd.kerdock_sparse_apply(h, Xc, eps, s_max, J, K, seed, t0=1 << 40, debug=True)
             r = planted_recall(out[3]["survivors"].cpu().numpy(), sup_c)

@@ -305,6 +305,37 @@ def test_non_finite_input_is_flagged(orc):
     h.destroy()
 
 
+def test_graph_capture_replays(orc):
+    """A call whose workspace is already sized allocates nothing and records
+    only kernels, so it can be captured in a HIP graph: every replay (with
+    unrelated eager work in between) reproduces the eager outputs."""
+    kd = need_gpu()
+    A = rand_A(300, 256, 3)
+    X = torch.from_numpy(unit_rows(40, 256, 4)).cuda()
+    h = prepare(kd, A, "bf16")
+    for fn in (kd.kerdock_sparse_apply, kd.kerdock_sparse_apply_shared):
+        out = (torch.empty((40, 24), dtype=torch.int32, device="cuda"),
+               torch.empty((40, 24), dtype=torch.float32, device="cuda"),
+               torch.empty((40,), dtype=torch.int32, device="cuda"))
+        fn(h, X, 0.05, 24, 64, 3, 5, t0=9, out=out)           # sizes the workspace
+        torch.cuda.synchronize()
+        ref = tuple(o.clone() for o in out)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn(h, X, 0.05, 24, 64, 3, 5, t0=9, out=out)
+        for r in range(3):
+            for o in out:
+                o.fill_(-3)
+            junk = torch.randn(1 << 20, device="cuda").sum()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            for a, b in zip(ref, out):
+                assert torch.equal(a, b)
+        del g
+    h.destroy()
+
+
 def test_zero_matrix(orc):
     kd = need_gpu()
     h = prepare(kd, np.zeros((40, 40), dtype=np.float32), "fp8")
