@@ -138,12 +138,14 @@ template <int LOGD> __device__ __forceinline__ void fwht_wave(float *v) {
         }
     }
     // lane bits
+    // the upper lane of a pair takes p - v, the lower v + p: one FMA with a
+    // per-lane sign, rounded exactly as the add or subtract
 #define KD_LANE_STAGE(H)                                                    \
     if constexpr ((H) < D) {                                                \
-        const bool upper = (lane & (H)) != 0;                               \
+        const float sg = (lane & (H)) != 0 ? -1.0f : 1.0f;                  \
         _Pragma("unroll") for (int q = 0; q < R; ++q) {                     \
-            float p = lane_xor<(H)>(v[q]);                                  \
-            v[q] = upper ? (p - v[q]) : (v[q] + p);                         \
+            const float p = lane_xor<(H)>(v[q]);                            \
+            v[q] = fmaf(v[q], sg, p);                                       \
         }                                                                   \
     }
     KD_LANE_STAGE(1)
@@ -184,16 +186,18 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_table_build(
     for (int t = threadIdx.x; t < WORDS; t += BUILD_THREADS) sbits[t] = signs[(size_t)b * WORDS + t];
     __syncthreads();
 
-    // load the signed, zero-padded row: element x = q*64 + lane
+    // load the signed, zero-padded row: element x = q*64 + lane (every load
+    // issued, from a clamped in-bounds address, and masked afterwards)
     float v[R];
+    const int rowc = row < m ? row : m - 1;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int x = q * 64 + lane;
-        const bool live = D >= 64 || lane < D;
-        float a = 0.f;
-        if (live && row < m && x < n) a = A[(size_t)row * n + x];
-        const uint32_t bit = live ? (sbits[x >> 5] >> (x & 31)) & 1u : 0u;
-        v[q] = bit ? -a : a;
+        const bool live = (D >= 64 || lane < D) && row < m && x < n;
+        const int xc = x < n ? x : n - 1;
+        const float a = A[(size_t)rowc * n + xc];
+        const uint32_t bit = (D >= 64 || lane < D) ? (sbits[x >> 5] >> (x & 31)) & 1u : 0u;
+        v[q] = live ? (bit ? -a : a) : 0.f;
     }
     fwht_wave<LOGD>(v);
 
@@ -222,7 +226,11 @@ __global__ __launch_bounds__(BUILD_THREADS) void k_table_build(
         for (int cc = threadIdx.x / THREADS_PER_COL; cc < COLS; cc += COLS_PER_PASS) {
             float vals[ROWS];
 #pragma unroll
-            for (int r = 0; r < ROWS; ++r) vals[r] = stage[cc * STAGE_PITCH + my_rows + r] / scale[r];
+            for (int r = 0; r < ROWS; ++r) {
+                // FP32 and BF16 tables have unit scales: no division
+                if constexpr (DT == KERDOCK_FP8E4M3) vals[r] = stage[cc * STAGE_PITCH + my_rows + r] / scale[r];
+                else vals[r] = stage[cc * STAGE_PITCH + my_rows + r];
+            }
             const size_t col = (size_t)b * D + c0 + cc;
             const size_t word = col * col_words + (size_t)(i0 + my_rows) / ROWS;
             out32[word] = S::pack(vals);
