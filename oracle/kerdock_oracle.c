@@ -40,6 +40,14 @@
  *   - the median of an even number of batch means is the mean of the two
  *     middle values; ties in |mu| are broken by the smaller row index;
  *   - the output keeps |v| >= eps (the definition of h_eps).
+ *
+ * Pins (tests/test_oracle_pins.py) check every routine against what the paper
+ * and the mathematics fix: field axioms, Proposition 7's Kerdock properties,
+ * Propositions 2 and 6, the estimator's exact mean and variance, numpy's
+ * Philox, torch's quantisers, Theorem 5's failure rate.  Parity unpinned: the
+ * particular sign patterns that the two conventions above (polynomial and
+ * basis) select among all valid Kerdock sets; the paper prints no example, so
+ * beyond those invariants only the agreement with the GPU path pins them.
  */
 #include <math.h>
 #include <stdint.h>
