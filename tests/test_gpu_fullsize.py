@@ -82,6 +82,55 @@ def test_fullsize(orc, wl, dtype):
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_fullsize_shared(orc, wl, dtype):
+    """The shared-draw form at the same size: vector t uses the draws of
+    group t // 64 (second Philox stream); the batch sums run on the matrix
+    cores in sixteen slices, so mu is held to the bound for J terms summed
+    in any order."""
+    kd = need_gpu()
+    w, A64, X64 = wl
+    h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
+    info = h.info
+    idx, val, cnt, dbg = kd.kerdock_sparse_apply_shared(h, torch.from_numpy(w.X).cuda(), EPS, S_MAX, J, K,
+                                                         SEED, debug=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in dbg.items()}
+    idx, val, cnt = idx.cpu().numpy(), val.cpu().numpy(), cnt.cpu().numpy()
+    h.destroy()
+    torch.cuda.empty_cache()
+    mode = {"f32": "exact", "bf16": "bf16", "fp8": "fp8"}[dtype]
+    Y = X64 @ A64.T
+    rec = []
+    for t in range(B):
+        S = g["survivors"][t]
+        assert np.array_equal(S, top_s(g["mu"][t], S_MAX))
+        gv = g["values"][t].astype(np.float64)
+        assert np.all(np.abs(gv - Y[t][S]) <= 1e-5 * np.abs(Y[t][S]) + 1e-9)
+        keep = S[np.abs(g["values"][t]) >= EPS]
+        assert np.array_equal(idx[t][:cnt[t]], keep)
+        sup = np.nonzero(np.abs(Y[t]) >= EPS)[0]
+        if len(sup):
+            rec.append(len(set(keep) & set(sup)) / len(sup))
+    assert np.mean(rec) >= 0.98
+    rng = np.random.default_rng(6)
+    for t in [0, 63, 64, B - 1]:
+        ls = orc.draw_samples(SEED, t // 64, J * K, info.L, stream=1)
+        assert np.array_equal(g["samples"][t].view(np.uint32).astype(np.int64), ls)
+        if t not in (0, B - 1):
+            continue
+        c64 = orc.table_entries(X64[t][None, :], ls, [0])[:, 0]
+        ct = coef_tol(X64[t], 2048)
+        assert np.all(np.abs(g["coef"][t] - c64) <= ct)
+        rows = np.unique(np.concatenate([g["survivors"][t][:8], rng.integers(0, 2048, 8)]))
+        ent = orc.table_entries(A64, ls, rows)
+        tolE, used = entry_tolerance(orc, ent, A64[rows], info.k, info.d, dtype)
+        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), J)
+        mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
+        dmu = np.abs(g["mu"][t][rows] - mu_o)
+        assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_basis_sums_reproduce_Ax(orc, wl, dtype):
     """One full basis reproduces Ax: the d design vectors of a basis are sqrt(d)
