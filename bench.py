@@ -199,7 +199,7 @@ def batched_form(kd, torch, np, workloads, args):
                        "recall across the forms" % (args.eps, args.recall, PLANTED_GRID[-1]),
            "eps_support_empty_fraction": float(np.mean([len(s) == 0 for e in exact for s in e[0]]))}
 
-    def run_form(dt, batched):
+    def run_form(dt, batched, shared=False):
         hs = [kd.kerdock_prepare(A, dt) for A in As]
         params = []
         for q, h in enumerate(hs):
@@ -221,6 +221,11 @@ def batched_form(kd, torch, np, workloads, args):
         def step(sidx):
             if batched:
                 kd.kerdock_multi_graph_launch(plan)
+            elif shared:
+                for q, h in enumerate(hs):
+                    p = params[q]
+                    kd.kerdock_sparse_apply_shared(h, Xs[q], args.eps, smax[q], p["J"], p["K"], p["seed"],
+                                                   t0=sidx * wl[q].batch // 64, out=outs[q])
             else:
                 for q, h in enumerate(hs):
                     p = params[q]
@@ -250,13 +255,16 @@ def batched_form(kd, torch, np, workloads, args):
         for h in hs:
             h.destroy()
         torch.cuda.empty_cache()
-        log("batched %s %s: %.1f x/s  %.2f ms/step" % (dt, "multi+graph" if batched else "per-matrix",
+        log("batched %s %s: %.1f x/s  %.2f ms/step" % (dt, "multi+graph" if batched else
+                                                       "per-matrix shared draws" if shared else "per-matrix",
                                                        form["x_per_s"], form["ms_per_step"]))
         return form
 
     res["plain_f32_per_matrix"] = run_form("f32", False)
     res["bf16_per_matrix"] = run_form("bf16", False)
     res["bf16_batched_graph"] = run_form("bf16", True)
+    if args.shared:
+        res["bf16_per_matrix_shared_draws"] = run_form("bf16", False, shared=True)
     res["speedup_vs_plain"] = res["bf16_batched_graph"]["x_per_s"] / res["plain_f32_per_matrix"]["x_per_s"]
     res["speedup_from_batching"] = res["bf16_batched_graph"]["x_per_s"] / res["bf16_per_matrix"]["x_per_s"]
     return res
