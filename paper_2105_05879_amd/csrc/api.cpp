@@ -363,9 +363,9 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
     KD_HIP(hipMemGetInfo(&free_b, &total_b));
     const size_t side = (size_t)m * n * 4 + nb * wpb * 4 + masks.size() * 2 + (size_t)h->pitch * 4;
     if (h->table_bytes + side + ((size_t)1 << 28) > free_b) {
+        const std::string msg = "table of " + std::to_string(h->table_bytes) + " bytes does not fit in free device memory";
         delete h;
-        return fail(KERDOCK_ERR_OOM, "table of " + std::to_string(h->table_bytes) +
-                                         " bytes does not fit in free device memory");
+        return fail(KERDOCK_ERR_OOM, msg);
     }
 #define KD_ALLOC(ptr, bytes)                                                      \
     do {                                                                          \

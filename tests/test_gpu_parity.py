@@ -269,6 +269,14 @@ def test_errors(orc):
     with pytest.raises(kd.KerdockError) as e:
         kd.kerdock_prepare(torch.zeros((4, 5000), device="cuda"))
     assert e.value.code == -2
+    with pytest.raises(kd.KerdockError) as e:
+        kd.kerdock_prepare(torch.zeros((16385, 8), device="cuda"))
+    assert e.value.code == -1
+    # a table that cannot fit in HBM (16384 x 8,392,704 FP32 entries, 550 GB)
+    with pytest.raises(kd.KerdockError) as e:
+        kd.kerdock_prepare(torch.zeros((16384, 4096), device="cuda"), "f32")
+    assert e.value.code == -3
+    torch.cuda.empty_cache()
     h = kd.kerdock_prepare(A)
     X = torch.from_numpy(unit_rows(2, 32, 1)).cuda()
     for kw, code in [(dict(eps=0.0, s_max=4, J=2, K=2), -1), (dict(eps=0.1, s_max=33, J=2, K=2), -1),
