@@ -109,18 +109,24 @@ template <int H> __device__ __forceinline__ float lane_xor(float v) {
 }
 
 // ----------------------------------------------------------- table build --
-// One workgroup = 16 waves = 16 consecutive rows of A and one Kerdock basis.
-// Wave r transforms row i0 + r: lane l holds elements x = q*64 + l (q < R),
-// the transform runs over the register index (bits 6..k-1) in registers and
-// over the lane index (bits 0..5) with cross-lane swizzles.  The d outputs of
-// the 16 rows are then staged, 1024 columns at a time, in LDS as [w][16 rows]
-// and written as contiguous 16-row segments of each column.  Workgroups that
+// One workgroup = 16 waves (8 for FP8) = as many consecutive rows of A and
+// one Kerdock basis.  Wave r transforms row i0 + r: lane l holds elements
+// x = q*64 + l (q < R), the transform runs over the register index (bits
+// 6..k-1) in registers and over the lane index (bits 0..5) with cross-lane
+// swizzles.  The d outputs of the rows are then staged, 1024 columns at a
+// time, in LDS as [w][rows] and written as contiguous row segments of each
+// column.  Workgroups that
 // run on the same XCD handle adjacent row strips of the same basis, so that
 // the segments of one column are merged in that XCD's L2 before reaching HBM.
-constexpr int BUILD_ROWS = 16;
-constexpr int BUILD_THREADS = BUILD_ROWS * 64;
+// rows per workgroup: 16 (FP32, BF16); 8 for FP8, whose 4-row packed stores
+// leave 16-row workgroups with too few store threads per column (measured
+// 44 ms -> 32 ms for the n = 2048 FP8 table)
+template <int DT> struct BuildShape {
+    static constexpr int ROWS = DT == KERDOCK_FP8E4M3 ? 8 : 16;
+    static constexpr int THREADS = ROWS * 64;
+    static constexpr int PITCH = ROWS + 1;    // +1 float: conflict-free staging
+};
 constexpr int STAGE_COLS = 1024;
-constexpr int STAGE_PITCH = BUILD_ROWS + 1;   // +1 float: conflict-free staging
 
 template <int LOGD> __device__ __forceinline__ void fwht_wave(float *v) {
     constexpr int D = 1 << LOGD;
@@ -158,13 +164,15 @@ template <int LOGD> __device__ __forceinline__ void fwht_wave(float *v) {
 }
 
 template <int LOGD, int DT>
-__global__ __launch_bounds__(BUILD_THREADS) void k_table_build(
+__global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
     const float *__restrict__ A, int m, int n, int pitch, const uint32_t *__restrict__ signs,
     const float *__restrict__ scales, void *__restrict__ table, int strips, int xcd_map) {
     constexpr int D = 1 << LOGD;
     constexpr int R = D >= 64 ? D / 64 : 1;
     constexpr int WORDS = D >= 32 ? D / 32 : 1;
     constexpr int COLS = D < STAGE_COLS ? D : STAGE_COLS;
+    constexpr int BUILD_ROWS = BuildShape<DT>::ROWS, BUILD_THREADS = BuildShape<DT>::THREADS;
+    constexpr int STAGE_PITCH = BuildShape<DT>::PITCH;
     __shared__ float stage[COLS * STAGE_PITCH];
     __shared__ uint32_t sbits[WORDS];
 
@@ -320,10 +328,10 @@ int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dt
 template <int LOGD, int DT>
 static int build_kd(const float *A, int m, int n, int pitch, const uint32_t *signs,
                     const float *scales, void *table, hipStream_t s) {
-    const int strips = pitch / BUILD_ROWS;
+    const int strips = pitch / BuildShape<DT>::ROWS;
     const int nb = (1 << LOGD) / 2;
     const int xcd_map = (strips % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_table_build<LOGD, DT>), dim3(strips * nb), dim3(BUILD_THREADS), 0, s, A,
+    hipLaunchKernelGGL((k_table_build<LOGD, DT>), dim3(strips * nb), dim3(BuildShape<DT>::THREADS), 0, s, A,
                        m, n, pitch, signs, scales, table, strips, xcd_map);
     KD_LAUNCH("k_table_build");
     return KERDOCK_OK;
