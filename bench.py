@@ -176,6 +176,54 @@ def calibrate_planted(kd, h, Xc, sup_c, eps, s_max, target, seed):
     return best
 
 
+def small_handles_form(kd, torch, np, workloads, args):
+    """Where the one-launch batched form pays: eight matrices of n = 256
+    with 32 x each (J = 512, K = 1, s_max = 256, BF16 tables), so that each
+    call is short and launch-bound; eight single-handle calls per step against
+    one graph replay of the persistent multi-handle launch."""
+    ws = workloads.batched(ns=(256,) * 8, counts=(32,) * 8, seed_X=workloads.SEED_X + 91)
+    hs = [kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), "bf16") for w in ws]
+    Xs = [torch.from_numpy(w.X).cuda() for w in ws]
+    params = [dict(J=512, K=1, seed=args.seed + q, t0=0) for q in range(8)]
+    smax = [256] * 8
+    outs = [(torch.empty((32, 256), dtype=torch.int32, device="cuda"),
+             torch.empty((32, 256), dtype=torch.float32, device="cuda"),
+             torch.empty((32,), dtype=torch.int32, device="cuda")) for _ in range(8)]
+    reps = 200
+    res = {"workload": "8 x (n = 256 Gaussian A, 32 x, s ~ U{4..64}), J = 512, K = 1, s_max = 256, BF16"}
+
+    def per_matrix(r):
+        for q, h in enumerate(hs):
+            p = params[q]
+            kd.kerdock_sparse_apply(h, Xs[q], args.eps, 256, p["J"], p["K"], p["seed"], t0=r * 32, out=outs[q])
+    for r in range(5):
+        per_matrix(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        per_matrix(r)
+    torch.cuda.synchronize()
+    res["per_matrix_x_per_s"] = 8 * 32 * reps / (time.perf_counter() - t0)
+    plan = kd.kerdock_multi_create(hs, Xs, params, args.eps, smax)
+    kd.kerdock_multi_autotune(plan)
+    kd.kerdock_multi_set_position(plan, [0] * 8)
+    for r in range(5):
+        kd.kerdock_multi_graph_launch(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        kd.kerdock_multi_graph_launch(plan)
+    torch.cuda.synchronize()
+    res["multi_graph_x_per_s"] = 8 * 32 * reps / (time.perf_counter() - t0)
+    res["speedup_from_batching"] = res["multi_graph_x_per_s"] / res["per_matrix_x_per_s"]
+    plan.destroy()
+    for h in hs:
+        h.destroy()
+    log("small handles: per-matrix %.0f x/s, multi+graph %.0f x/s (%.2fx)"
+        % (res["per_matrix_x_per_s"], res["multi_graph_x_per_s"], res["speedup_from_batching"]))
+    return res
+
+
 def batched_form(kd, torch, np, workloads, args):
     """Three Gaussian A (n = 256, 1024, 4096) serving 512 / 1024 / 2560 x with
     per-x sparsity s ~ U{4..64}, s_max = min(640, n): the plain FP32 form as
@@ -265,6 +313,7 @@ def batched_form(kd, torch, np, workloads, args):
     res["bf16_batched_graph"] = run_form("bf16", True)
     if args.shared:
         res["bf16_per_matrix_shared_draws"] = run_form("bf16", False, shared=True)
+    res["small_handles"] = small_handles_form(kd, torch, np, workloads, args)
     res["speedup_vs_plain"] = res["bf16_batched_graph"]["x_per_s"] / res["plain_f32_per_matrix"]["x_per_s"]
     res["speedup_from_batching"] = res["bf16_batched_graph"]["x_per_s"] / res["bf16_per_matrix"]["x_per_s"]
     return res
