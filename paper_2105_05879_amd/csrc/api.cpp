@@ -30,9 +30,10 @@ int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int 
 int gather_chunk_max();
 int launch_select(const SelArgs &a, int batch, hipStream_t s);
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
-int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs, uint64_t seed,
-                       int64_t t0, int N, int8_t *digits, int2 *xscale, uint32_t *ell, float *coef,
-                       uint32_t *dbg_samples, float *dbg_coef, hipStream_t s);
+int launch_shared_coef(kerdock_dtype dt, const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs,
+                       uint64_t seed, int64_t t0, int J, int K, int8_t *digits, int2 *xscale, uint32_t *ell,
+                       float *coef, uint32_t *dbg_samples, float *dbg_coef, hipStream_t s);
+size_t shared_coef_floats(kerdock_dtype dt, int batch, int J, int K);
 int shared_n_pad(int n);
 int shared_splits(int J);
 int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch, int J, int K, const uint32_t *ell,
@@ -260,6 +261,7 @@ int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, 
                      int *best_chunk, int *best_unroll, float *best_ms) {
     if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
     if (!X || batch < 1 || J < 1 || K < 1 || K > 32) return fail(KERDOCK_ERR_INVALID_ARG, "autotune: bad arguments");
+    if ((int64_t)J * K > ((int64_t)1 << 31) - 64) return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const GatherShape gs = gather_shape(h->dtype, h->pitch);
     std::vector<int> unrolls;
@@ -417,6 +419,7 @@ int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max) {
     if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
     if (batch < 0 || J < 1 || K < 1 || K > 32 || s_max < 1 || s_max > h->m)
         return fail(KERDOCK_ERR_INVALID_ARG, "reserve: invalid sizes");
+    if ((int64_t)J * K > ((int64_t)1 << 31) - 64) return fail(KERDOCK_ERR_INVALID_ARG, "J K must stay below 2^31");
     KD_HIP(hipSetDevice(h->device));
     return ensure_workspace(h, workspace_layout(h, batch, J, K, s_max, chunk_for(h, J, 0)).total);
 }
@@ -441,7 +444,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     size_t off = 0;
     const int splits = shared_splits(J);
     const size_t o_partial = off; off += align256((size_t)batch * K * splits * h->pitch * 4);
-    const size_t o_coef = off;    off += align256(groups * KERDOCK_SHARED_TILE * N * 4);
+    const size_t o_coef = off;    off += align256(shared_coef_floats(h->dtype, batch, J, K) * 4);
     const size_t o_ell = off;     off += align256(groups * N * 4);
     const size_t o_surv = off;    off += align256((size_t)batch * s_max * 4);
     const size_t o_nsurv = off;   off += align256((size_t)batch * 4);
@@ -468,8 +471,8 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     if (timed && !h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
     if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
-    rc = launch_shared_coef(X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, N, digits, xscale, ell, coef,
-                            p->dbg_samples, p->dbg_coef, s);
+    rc = launch_shared_coef(h->dtype, X, batch, h->n, h->k, h->L, h->signs, p->seed, p->t0, J, K, digits, xscale, ell,
+                            coef, p->dbg_samples, p->dbg_coef, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
     if (rc == KERDOCK_OK) rc = launch_shared_gemm(h->dtype, h->table, h->pitch, batch, J, K, ell, coef, partial, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));

@@ -328,6 +328,7 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
     if (!p) return fail(KERDOCK_ERR_INVALID_ARG, "params is NULL");
     if (B < 0 || !(eps > 0.f) || !(eps < INFINITY) || s_max < 1 || s_max > h->m)
         return fail(KERDOCK_ERR_INVALID_ARG, "bad batch, eps or s_max");
+    if ((int64_t)B * s_max >= ((int64_t)1 << 31)) return fail(KERDOCK_ERR_INVALID_ARG, "batch s_max must stay below 2^31");
     if (B == 0) return KERDOCK_OK;
     if (!X || !out_idx || !out_val || !out_cnt || !fallback) return fail(KERDOCK_ERR_INVALID_ARG, "NULL pointer");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

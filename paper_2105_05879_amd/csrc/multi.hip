@@ -261,7 +261,8 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         if (!h) { delete pl; return fail(KERDOCK_ERR_NOT_PREPARED, "multi: NULL handle"); }
         if (h->dtype != pl->dtype) { delete pl; return fail(KERDOCK_ERR_INVALID_ARG, "multi: handles must share the table dtype"); }
         if (batch[q] < 1 || !X[q] || !out_idx[q] || !out_val[q] || !out_cnt[q] || s_max[q] < 1 || s_max[q] > h->m ||
-            p->J < 1 || p->K < 1 || p->K > 32 || (int64_t)p->J * p->K > ((int64_t)1 << 31) - 64) {
+            p->J < 1 || p->K < 1 || p->K > 32 || (int64_t)p->J * p->K > ((int64_t)1 << 31) - 64 ||
+            (int64_t)batch[q] * s_max[q] >= ((int64_t)1 << 31)) {
             delete pl;
             return fail(KERDOCK_ERR_INVALID_ARG, "multi: invalid batch, pointer, s_max, J or K for handle " + std::to_string(q));
         }

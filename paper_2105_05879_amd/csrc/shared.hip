@@ -9,10 +9,14 @@
 //     Y_k[i][t] = sum_{j in batch k} T[l_j][i] c_j(x_t),
 // form the matrix product of the m x J gathered table columns T_{S_k} and the
 // J x 64 coefficient block C_k.  Each table column is then read once per
-// group instead of once per vector, and the product runs on the FP32 matrix
-// cores (16 x 16 x 4 MFMA), with BF16 and FP8 entries widened to FP32 on the
-// way into LDS.  The batch means, median, selection and survivor dots are
-// those of the per-vector form (partials with one chunk per batch).
+// group instead of once per vector.  With an FP32 table the product runs on
+// the FP32 matrix cores (16 x 16 x 4 MFMA).  BF16 and FP8 entries are exact
+// BF16 values, so there it runs on the BF16 matrix cores (16 x 16 x 32 MFMA)
+// with every coefficient split exactly into three BF16 parts: each product
+// of an entry and a part is exact in FP32, and only the FP32 accumulation
+// rounds, as in the FP32 product.  The batch means, median, selection and
+// survivor dots are those of the per-vector form (partials with one chunk
+// per batch).
 #include "apply_device.hpp"
 
 namespace kd {
@@ -73,9 +77,14 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
 }
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// k_shared_coef: grid (ceil(N / 64), groups), 256 threads; coef[g][j][t mod
-// 64] (the 64 vectors of a draw contiguous).  Wave w takes
+// k_shared_coef: grid (K ceil(J / 64), groups), 256 threads; block x takes
+// draws kb J + 64 jb .. + 63 of batch kb = x / ceil(J / 64) (never past the
+// batch).  Output layout: by_vector == 0, coef[g][j][t mod 64] (the 64
+// vectors of a draw contiguous); by_vector != 0, coef[g][t mod 64][kb JP + j
+// - kb J] with JP = J rounded up to 64 (the draws of a vector and batch
+// contiguous).  Wave w takes
 // draws j0 + 16 w .. + 15 of group g (the 16 rows of its MFMA blocks) against
 // the group's 64 vectors (4 column blocks) and 4 digits: 16 accumulators.
 // Per step of 64 coordinates the digits of the 64 vectors go through LDS;
@@ -84,7 +93,8 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 // give every lane the same 16 consecutive coordinates of the step.
 __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
                                                      const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
-                                                     int batch, int N, const int8_t *__restrict__ digits,
+                                                     int batch, int J, int K, int by_vector,
+                                                     const int8_t *__restrict__ digits,
                                                      const int2 *__restrict__ xscale, uint32_t *__restrict__ ell,
                                                      float *__restrict__ coef, uint32_t *__restrict__ dbg_samples,
                                                      float *__restrict__ dbg_coef) {
@@ -101,16 +111,18 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
     }
     // this lane's draw: row lane % 16 of the wave's block
     const int row = lane & 15;
-    const int j = blockIdx.x * 64 + wave * 16 + row;
+    const int N = J * K, JP = (J + 63) & ~63, jblocks = JP / 64;
+    const int kb = blockIdx.x / jblocks, jb0 = (blockIdx.x % jblocks) * 64 + wave * 16;
+    const int j = kb * J + jb0 + row;
     uint32_t my_l = 0;
-    if (j < N) {
+    if (jb0 + row < J) {
         uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + g), 1, 0};
         philox4x64_10(c4, seed, 0);
         const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
         my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
     }
     const uint32_t bb = my_l >> k, ww = my_l & (uint32_t)(d - 1);
-    const bool kerdock_row = j < N && (int)bb < d / 2;
+    const bool kerdock_row = jb0 + row < J && (int)bb < d / 2;
     const uint32_t w16 = (ww & 1u ? 0xAAAAu : 0u) ^ (ww & 2u ? 0xCCCCu : 0u) ^ (ww & 4u ? 0xF0F0u : 0u) ^
                          (ww & 8u ? 0xFF00u : 0u);
     const int kq = (lane >> 4) * 16;                 // this lane's 16 coordinates within a step
@@ -169,12 +181,15 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
     // D block: lane holds draws 4 (lane / 16) + v of the wave's 16, vector
     // column lane % 16 of block c
     const float sqrt_d = sqrtf((float)d);
+    float cv[4][4];                                  // [vector block][draw v]
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int r = 4 * (lane >> 4) + v;
         const uint32_t l_r = __shfl(my_l, r);
-        const int jr = blockIdx.x * 64 + wave * 16 + r;
-        if (jr >= N) continue;
+        const int jr = kb * J + jb0 + r;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cv[c][v] = 0.f;
+        if (jb0 + r >= J) continue;
         const uint32_t b_r = l_r >> k, w_r = l_r & (uint32_t)(d - 1);
         const bool ident = (int)b_r == d / 2;
 #pragma unroll
@@ -191,12 +206,25 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                     ((int64_t)acc[2][c][v] << 16) + ((int64_t)acc[3][c][v] << 24);
                 cf = sc.y ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
             }
-            coef[((size_t)g * N + jr) * ST + tv] = cf;
+            cv[c][v] = cf;
+            if (!by_vector) coef[((size_t)g * N + jr) * ST + tv] = cf;
             if (tv == 0) ell[(size_t)g * N + jr] = l_r;
             if (dbg_samples) {
                 dbg_samples[(size_t)t * N + jr] = l_r;
                 dbg_coef[(size_t)t * N + jr] = cf;
             }
+        }
+    }
+    if (by_vector) {
+        // four consecutive draws of one vector per lane: one 16-byte store
+        // (zeros past the batch end, inside the row's padding to JP)
+        const size_t pos = (size_t)kb * JP + jb0 + 4 * (lane >> 4);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int tv = c * 16 + row;
+            if (tv < nx)
+                *reinterpret_cast<f32x4 *>(coef + ((size_t)g * ST + tv) * ((size_t)K * JP) + pos) =
+                    f32x4{cv[c][0], cv[c][1], cv[c][2], cv[c][3]};
         }
     }
 }
@@ -226,8 +254,6 @@ __device__ __forceinline__ void widen(const u32x4 raw, float *v) {
         }
     }
 }
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Draws of a batch are split into `splits` consecutive slices (a function of
 // J alone, so results never depend on the batch size), each summed by its
@@ -332,18 +358,232 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
         }
 }
 
-int launch_shared_coef(const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs, uint64_t seed,
-                       int64_t t0, int N, int8_t *digits, int2 *xscale, uint32_t *ell, float *coef,
-                       uint32_t *dbg_samples, float *dbg_coef, hipStream_t s) {
+// ---------------------------------------------- BF16 matrix-core product --
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+constexpr int SB_BM = 256;                    // table rows per workgroup
+constexpr int SB_BK = 64;                     // draws per LDS stage
+constexpr int SB_LD = SB_BK + 8;              // LDS row: 144 bytes, an odd number of 16-byte units
+
+// First draw of slice sp: J sp / splits rounded up to a multiple of four
+// (the coefficient rows then start 16-byte aligned); slice `splits` ends at J.
+__device__ __forceinline__ int slice_begin(int J, int sp, int splits) {
+    if (sp >= splits) return J;
+    return min(J, (int)((((long long)J * sp) / splits + 3) & ~3ll));
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(__bf16 v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
+
+// c = hi + mid + lo exactly: each step rounds to BF16 and keeps the rounding
+// error, which FP32 holds exactly; after two steps at most 8 significant bits
+// of c's 24 are left, so the third part is exact.  The parts come back as
+// packed pairs: p[q] = part q of c0 (low half) and of c1 (high half).
+__device__ __forceinline__ void split3x2(float c0, float c1, uint32_t p[3]) {
+    const __bf16 h0 = (__bf16)c0, h1 = (__bf16)c1;
+    const float r0 = c0 - (float)h0, r1 = c1 - (float)h1;
+    const __bf16 m0 = (__bf16)r0, m1 = (__bf16)r1;
+    const __bf16 l0 = (__bf16)(r0 - (float)m0), l1 = (__bf16)(r1 - (float)m1);
+    p[0] = bf16_bits(h0) | (bf16_bits(h1) << 16);
+    p[1] = bf16_bits(m0) | (bf16_bits(m1) << 16);
+    p[2] = bf16_bits(l0) | (bf16_bits(l1) << 16);
+}
+
+// k_shared_gemm16: the product for BF16 and FP8 tables.  Grid (ceil(pitch /
+// 256), K splits, groups), 256 threads; output as k_shared_gemm, slice
+// bounds slice_begin.  Coefficients in the by-vector layout (k_shared_coef,
+// by_vector != 0).  Per stage of 64 draws:
+//   A: thread (ad, ar) = (tid % 8, tid / 8) loads rows i0 + 8 ar .. + 7 of draws
+//      8 ad .. + 7 (FP8 entries widened to BF16, exact) and transposes the
+//      8 x 8 block in registers, so that As[row][draw] holds the draws of a row
+//      contiguous, as the MFMA operand wants them (8 draws per lane);
+//   B: thread (bt, bq) = (tid % 64, tid / 64) loads draws 16 bq .. + 15 of
+//      vector bt and writes the three parts to Bs[part][vector][draw].
+// With rows of 9 16-byte units, the 16 lanes of an LDS access always meet 16
+// distinct bank groups, on the staging writes and on the operand reads.
+// Wave w owns rows 128 (w % 2) .. + 127 and vectors 32 (w / 2) .. + 31: 8 x 2
+// MFMA blocks, 3 MFMAs (one per part) per block and 32 draws.
+template <int DT>
+__global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__restrict__ table, int col_bytes,
+                                                       int pitch, int batch, int J, int K, int N, int splits,
+                                                       const uint32_t *__restrict__ ell,
+                                                       const float *__restrict__ coef,
+                                                       float *__restrict__ partial) {
+    static_assert(DT == KERDOCK_BF16 || DT == KERDOCK_FP8E4M3, "BF16-exact tables only");
+    constexpr int EB = DT == KERDOCK_BF16 ? 2 : 1;   // bytes per entry
+    constexpr int LW = 2 * EB;                       // 32-bit words per 8 rows
+    __shared__ __align__(16) uint16_t As[SB_BM][SB_LD];
+    __shared__ __align__(16) uint16_t Bs[3][ST][SB_LD];
+    const int g = blockIdx.z, kb = blockIdx.y / splits, sp = blockIdx.y % splits, i0 = blockIdx.x * SB_BM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nx = min(ST, batch - g * ST);
+    const int js = slice_begin(J, sp, splits);
+    const int Jl = slice_begin(J, sp + 1, splits) - js;
+    const int JP = (J + 63) & ~63;
+    const uint32_t *__restrict__ el = ell + (size_t)g * N + (size_t)kb * J + js;
+    const int ad = tid & 7, ar = tid >> 3;
+    const int arow = i0 + 8 * ar;
+    const bool arow_ok = arow < pitch;                // pitch is a multiple of 64
+    const int bt = tid & 63, bq = tid >> 6;
+    const float *__restrict__ cf = coef + ((size_t)g * ST + bt) * ((size_t)K * JP) + (size_t)kb * JP + js;
+    const bool bt_ok = bt < nx;
+    const int wr = (wave & 1) * 128, wv = (wave >> 1) * 32;
+
+    f32x4 acc[8][2];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // The loads are branch-free (indices clamped into the slice, values
+    // masked), so that all of a stage's loads are in flight together; the
+    // draw indices are loaded one stage ahead of the table entries they
+    // address.
+    const int Jq = (Jl - 1) & ~3;                  // last aligned quad of the slice
+    const float *__restrict__ cfr = bt_ok ? cf : coef + ((size_t)g * ST) * ((size_t)K * JP) + (size_t)kb * JP + js;
+    const size_t aoff = (size_t)(arow_ok ? arow : 0) * EB;
+    uint32_t lv[8];
+    uint32_t ra[8][LW];
+    f32x4 rb[4];
+    auto fetch_ell = [&](int j0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) lv[e] = el[min(j0 + 8 * ad + e, Jl - 1)];
+    };
+    auto fetch = [&](int j0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const unsigned char *src = table + (size_t)lv[e] * (size_t)col_bytes + aoff;
+            if constexpr (DT == KERDOCK_BF16) {
+                const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src));
+                ra[e][0] = v.x; ra[e][1] = v.y; ra[e][2] = v.z; ra[e][3] = v.w;
+            } else {
+                const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(src));
+                ra[e][0] = v.x; ra[e][1] = v.y;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            rb[u] = *reinterpret_cast<const f32x4 *>(cfr + min(j0 + 16 * bq + 4 * u, Jq));
+    };
+
+    fetch_ell(0);
+    fetch(0);
+    fetch_ell(SB_BK);
+    for (int j0 = 0; j0 < Jl; j0 += SB_BK) {
+        {
+            // rows as packed BF16 pairs: q[e][w] holds rows 2w, 2w + 1 of draw e
+            // (values past the slice end or the last row are masked here,
+            // where the loads are consumed)
+            uint32_t q[8][4];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool ok = j0 + 8 * ad + e < Jl && arow_ok;
+                if constexpr (DT == KERDOCK_BF16) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) q[e][w] = ok ? ra[e][w] : 0u;
+                } else {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t word = ok ? ra[e][h] : 0u;
+                        const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)word, false);
+                        const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)word, true);
+                        q[e][2 * h] = (__float_as_uint(lo[0]) >> 16) | (__float_as_uint(lo[1]) & 0xFFFF0000u);
+                        q[e][2 * h + 1] = (__float_as_uint(hi[0]) >> 16) | (__float_as_uint(hi[1]) & 0xFFFF0000u);
+                    }
+                }
+            }
+            // transpose: row r gets draws 2 v, 2 v + 1 in word v
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                u32x4 even, odd;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t a = q[2 * v][w], b = q[2 * v + 1][w];
+                    even[v] = (a & 0xFFFFu) | (b << 16);
+                    odd[v] = (a >> 16) | (b & 0xFFFF0000u);
+                }
+                *reinterpret_cast<u32x4 *>(&As[8 * ar + 2 * w][8 * ad]) = even;
+                *reinterpret_cast<u32x4 *>(&As[8 * ar + 2 * w + 1][8 * ad]) = odd;
+            }
+        }
+        {
+            uint32_t p[4][2][3];                     // [u][pair][part]
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jj = j0 + 16 * bq + 4 * u;
+                float c[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) c[e] = (bt_ok && jj + e < Jl) ? rb[u][e] : 0.f;
+                split3x2(c[0], c[1], p[u][0]);
+                split3x2(c[2], c[3], p[u][1]);
+            }
+#pragma unroll
+            for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    *reinterpret_cast<u32x4 *>(&Bs[part][bt][16 * bq + 8 * h]) =
+                        u32x4{p[2 * h][0][part], p[2 * h][1][part], p[2 * h + 1][0][part], p[2 * h + 1][1][part]};
+        }
+        __syncthreads();
+        if (j0 + SB_BK < Jl) {
+            fetch(j0 + SB_BK);
+            fetch_ell(j0 + 2 * SB_BK);
+        }
+#pragma unroll
+        for (int kk = 0; kk < SB_BK; kk += 32) {
+            const int kc = kk + 8 * (lane >> 4);
+            bf16x8 fa[8];
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+                fa[a] = *reinterpret_cast<const bf16x8 *>(&As[wr + 16 * a + (lane & 15)][kc]);
+#pragma unroll
+            for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(&Bs[part][wv + 16 * b + (lane & 15)][kc]);
+#pragma unroll
+                    for (int a = 0; a < 8; ++a)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a][b], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // D block (a, b): lane holds rows 4 (lane / 16) + v, v < 4, of column lane % 16
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int row = i0 + wr + a * 16 + 4 * (lane >> 4);
+            const int tt = wv + b * 16 + (lane & 15);
+            if (tt < nx && row < pitch)
+                *reinterpret_cast<f32x4 *>(partial + (((size_t)(g * ST + tt) * K + kb) * splits + sp) * pitch + row) =
+                    acc[a][b];
+        }
+}
+
+// Coefficient layout of the product for a table type: by vector for the
+// BF16 product, by draw for the FP32 one.
+bool shared_by_vector(kerdock_dtype dt) { return dt != KERDOCK_F32; }
+
+// floats of the coefficient buffer
+size_t shared_coef_floats(kerdock_dtype dt, int batch, int J, int K) {
+    const size_t groups = ((size_t)batch + ST - 1) / ST;
+    const size_t JP = ((size_t)J + 63) & ~(size_t)63;
+    return groups * ST * (shared_by_vector(dt) ? (size_t)K * JP : (size_t)J * K);
+}
+
+int launch_shared_coef(kerdock_dtype dt, const float *X, int batch, int n, int k, int64_t L, const uint32_t *signs,
+                       uint64_t seed, int64_t t0, int J, int K, int8_t *digits, int2 *xscale, uint32_t *ell,
+                       float *coef, uint32_t *dbg_samples, float *dbg_coef, hipStream_t s) {
     const int groups = (batch + ST - 1) / ST;
-    const int nb = (N + 63) / 64;
+    const long long nb = (long long)K * ((J + 63) / 64);
+    if (nb > 2147483647ll) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: too many draws");
     if (groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: launch too large");
     const int n_pad = shared_n_pad(n);
     if (n <= 2048) hipLaunchKernelGGL(k_x_digits<1>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
     else hipLaunchKernelGGL(k_x_digits<2>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
     KD_LAUNCH("k_x_digits");
-    hipLaunchKernelGGL(k_shared_coef, dim3(nb, groups), dim3(256), 0, s, X, n, n_pad, k, L, signs, seed, t0, batch, N,
-                       digits, xscale, ell, coef, dbg_samples, dbg_coef);
+    hipLaunchKernelGGL(k_shared_coef, dim3((unsigned)nb, groups), dim3(256), 0, s, X, n, n_pad, k, L, signs, seed, t0,
+                       batch, J, K, shared_by_vector(dt) ? 1 : 0, digits, xscale, ell, coef, dbg_samples, dbg_coef);
     KD_LAUNCH("k_shared_coef");
     return KERDOCK_OK;
 }
@@ -354,6 +594,7 @@ int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch
     if (groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: batch too large");
     const int splits = shared_splits(J);
     dim3 grid((pitch + SG_BM - 1) / SG_BM, K * splits, groups);
+    dim3 grid16((pitch + SB_BM - 1) / SB_BM, K * splits, groups);
     const unsigned char *tb = reinterpret_cast<const unsigned char *>(table);
     const int cb = pitch * (int)dtype_bytes(dt), N = J * K;
     switch (dt) {
@@ -362,12 +603,12 @@ int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch
                            coef, partial);
         break;
     case KERDOCK_BF16:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_BF16>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
-                           coef, partial);
+        hipLaunchKernelGGL(k_shared_gemm16<KERDOCK_BF16>, grid16, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits,
+                           ell, coef, partial);
         break;
     case KERDOCK_FP8E4M3:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_FP8E4M3>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
-                           coef, partial);
+        hipLaunchKernelGGL(k_shared_gemm16<KERDOCK_FP8E4M3>, grid16, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N,
+                           splits, ell, coef, partial);
         break;
     }
     KD_LAUNCH("k_shared_gemm");

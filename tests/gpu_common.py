@@ -41,15 +41,30 @@ def quant_interval_check(orc, gpu, lo, hi, mode, scale=None):
     return (gpu >= np.minimum(qlo, qhi) - 1e-30 * np.abs(qlo)) & (gpu <= np.maximum(qlo, qhi) + 1e-30 * np.abs(qhi))
 
 
-def mu_tolerance(cols, coef, J, K, tolT, tolc, chunk):
+def shared_terms(J, dtype):
+    """Rounded FP32 additions behind one batch sum of the shared-draw form,
+    each term bounded by |T c|: the FP32 product sums J products in some
+    order; the BF16 product (BF16 and FP8 tables) sums three exact products
+    per draw (c split into three BF16 parts whose magnitudes add up to at most
+    (1 + 2^-7) |c|) within slices of at most ceil(J / splits) + 3 draws, then
+    the slices."""
+    if dtype == "f32":
+        return J + 1
+    splits = min(16, max(1, J // 2048))
+    return int(np.ceil((3 * (-(-J // splits) + 3) + splits) * (1 + 2.0 ** -7)))
+
+
+def mu_tolerance(cols, coef, J, K, tolT, tolc, chunk, terms=None):
     """Bound on |mu_gpu - mu_oracle| per row from the per-draw errors of the
     table entries (tolT, per draw and row) and coefficients (tolc, per draw), plus the
-    FP32 accumulation over at most `chunk` FMAs and J/chunk partial sums.
+    FP32 accumulation over at most `chunk` FMAs and J/chunk partial sums, or,
+    when `terms` is given, over `terms` additions in any order.
     The median is 1-Lipschitz in the max norm, so the batch bound carries over."""
     N = J * K
     ac = np.abs(coef)[:, None]
     aT = np.abs(cols)
-    per = ac * tolT + aT * tolc[:, None] + (min(chunk, J) + J // max(1, chunk) + 4) * U32 * ac * aT
+    adds = (min(chunk, J) + J // max(1, chunk)) if terms is None else terms
+    per = ac * tolT + aT * tolc[:, None] + (adds + 4) * U32 * ac * aT
     per = per.reshape(K, J, -1).sum(1) / J
     return per.max(0) + 4 * U32 * np.abs((cols * coef[:, None]).reshape(K, J, -1).sum(1) / J).max(0)
 

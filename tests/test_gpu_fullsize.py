@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import U32, coef_tol, entry_tolerance, mu_tolerance, need_gpu
+from gpu_common import U32, coef_tol, entry_tolerance, mu_tolerance, need_gpu, shared_terms
 from paper_2105_05879_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -86,8 +86,8 @@ def test_fullsize(orc, wl, dtype):
 def test_fullsize_shared(orc, wl, dtype):
     """The shared-draw form at the same size: vector t uses the draws of
     group t // 64 (second Philox stream); the batch sums run on the matrix
-    cores in sixteen slices, so mu is held to the bound for J terms summed
-    in any order."""
+    cores in sixteen slices, so mu is held to the bound for the product's
+    terms summed in any order."""
     kd = need_gpu()
     w, A64, X64 = wl
     h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
@@ -125,7 +125,7 @@ def test_fullsize_shared(orc, wl, dtype):
         rows = np.unique(np.concatenate([g["survivors"][t][:8], rng.integers(0, 2048, 8)]))
         ent = orc.table_entries(A64, ls, rows)
         tolE, used = entry_tolerance(orc, ent, A64[rows], info.k, info.d, dtype)
-        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), J)
+        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), J, shared_terms(J, dtype))
         mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
         dmu = np.abs(g["mu"][t][rows] - mu_o)
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()

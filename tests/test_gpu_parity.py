@@ -136,7 +136,7 @@ def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, e
     return A64, X64, g, r, info, eps
 
 
-def check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, tau=0.0, chunk=512):
+def check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, tau=0.0, chunk=512, terms=None):
     k, d, n = info.k, info.d, A64.shape[1]
     exceptions = 0
     for t in range(X64.shape[0]):
@@ -148,7 +148,7 @@ def check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, tau=0.0, chun
         # median of means
         ref = np.stack([orc.table_column(A64, l) for l in r["samples"][t]])
         tolE, used = entry_tolerance(orc, ref, A64, k, d, dtype)
-        mt = mu_tolerance(used, r["coef"][t], J, K, tolE, np.full(J * K, ct), chunk)
+        mt = mu_tolerance(used, r["coef"][t], J, K, tolE, np.full(J * K, ct), chunk, terms)
         dmu = np.abs(g["mu"][t] - r["mu"][t])
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
         # selection
@@ -287,6 +287,13 @@ def test_errors(orc):
         with pytest.raises(kd.KerdockError) as e:
             kd.kerdock_sparse_apply(h, X, seed=0, **kw)
         assert e.value.code == code
+    # J K beyond the 32-bit draw counter, in every entry point that takes it
+    for call in (lambda: kd.kerdock_sparse_apply(h, X, 0.1, 4, 1 << 30, 2, 0),
+                 lambda: kd.kerdock_reserve(h, 2, 1 << 30, 2, 4),
+                 lambda: kd.kerdock_autotune(h, X, 1 << 30, 2)):
+        with pytest.raises(kd.KerdockError) as e:
+            call()
+        assert e.value.code == -1
     # empty batch is a no-op
     out = kd.kerdock_sparse_apply(h, X[:0], 0.1, 4, 2, 2, 0)
     assert out[0].shape == (0, 4)

@@ -1,15 +1,16 @@
 """Shared-draw form on the GPU: the draws of a group of 64 rows of X come
 from one stream position, the batch sums run as a matrix product on the
-FP32 matrix cores.  Against the FP64 oracle in its shared-draw mode: draws
-bit-exact, coefficients and median of means within the FP32 bounds (the
-summation order of the matrix product is not sequential, so the bound for
-J terms in any order is used), selections up to near-ties, survivor values
-1e-5 relative."""
+matrix cores (FP32 for FP32 tables; BF16 with coefficients split into three
+exact BF16 parts for BF16 and FP8 tables).  Against the FP64 oracle in its
+shared-draw mode: draws bit-exact, coefficients and median of means within
+the FP32 bounds (the summation order of the matrix product is not
+sequential, so the bound for its number of terms in any order is used),
+selections up to near-ties, survivor values 1e-5 relative."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import need_gpu
+from gpu_common import need_gpu, shared_terms
 from test_gpu_parity import check_case, rand_A, unit_rows
 
 pytestmark = pytest.mark.gpu
@@ -23,6 +24,7 @@ SHARED_CASES = [
     (300, 100, 130, 37, 2, 40),
     (70, 300, 65, 64, 1, 30),
     (1000, 1000, 64, 130, 2, 60),
+    (64, 64, 70, 4099, 1, 16),          # two slices, the second with a ragged end
 ]
 
 
@@ -54,7 +56,7 @@ def test_shared_parity(orc, m, n, B, J, K, s_max, dtype):
     # rows of one group share their draws
     for t in range(B):
         assert np.array_equal(g["samples"][t], g["samples"][(t // TILE) * TILE])
-    exc = check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, chunk=J)
+    exc = check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, chunk=J, terms=shared_terms(J, dtype))
     assert exc <= 1
 
 
