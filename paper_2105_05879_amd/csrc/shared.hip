@@ -79,18 +79,30 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+constexpr int SC_DRAWS = 64;                  // draws per coefficient workgroup (16 per wave)
+constexpr int SC_LD = 80;                      // bytes per LDS row of 64 digits
+
+// Sign bits to +-1 bytes: bit q of the 4-bit value m goes to byte q (the
+// four shifted copies m << 7 q do not overlap), then 0 -> 0x01, 1 -> 0xFF.
+__device__ __forceinline__ int sign_bytes4(uint32_t m) {
+    const uint32_t bits = (m * 0x00204081u) & 0x01010101u;
+    return (int)(0x01010101u + bits * 0xFEu);
+}
+
 // k_shared_coef: grid (K ceil(J / 64), groups), 256 threads; block x takes
 // draws kb J + 64 jb .. + 63 of batch kb = x / ceil(J / 64) (never past the
 // batch).  Output layout: by_vector == 0, coef[g][j][t mod 64] (the 64
 // vectors of a draw contiguous); by_vector != 0, coef[g][t mod 64][kb JP + j
 // - kb J] with JP = J rounded up to 64 (the draws of a vector and batch
-// contiguous).  Wave w takes
-// draws j0 + 16 w .. + 15 of group g (the 16 rows of its MFMA blocks) against
-// the group's 64 vectors (4 column blocks) and 4 digits: 16 accumulators.
-// Per step of 64 coordinates the digits of the 64 vectors go through LDS;
-// the sign rows are made in registers from the sign bitmaps and the Walsh
-// pattern of w, sixteen coordinates (one 128-bit operand) per lane; A and B
-// give every lane the same 16 consecutive coordinates of the step.
+// contiguous).  Wave w takes draws 16 w .. + 15 of the block (the 16 rows of
+// its MFMA blocks) against the group's 64 vectors (4 column blocks) and 4
+// digits: 16 accumulators.  Per step of 64 coordinates the digits of the 64
+// vectors go through LDS; the sign rows are made in registers from the sign
+// bitmaps and the Walsh pattern of w, sixteen coordinates (one 128-bit
+// operand) per lane; A and B give every lane the same 16 consecutive
+// coordinates of the step.  The next step's digits and sign word are loaded
+// before this step's MFMAs, with clamped indices and no branches, so that no
+// wait covers more than the loads it needs.
 __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
                                                      const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
                                                      int batch, int J, int K, int by_vector,
@@ -98,76 +110,68 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                                      const int2 *__restrict__ xscale, uint32_t *__restrict__ ell,
                                                      float *__restrict__ coef, uint32_t *__restrict__ dbg_samples,
                                                      float *__restrict__ dbg_coef) {
-    __shared__ uint64_t lut[256];                   // 8 sign bits -> 8 bytes of +-1
-    __shared__ __align__(16) int8_t Bs[4][ST][64];  // [digit][vector][coordinate]
+    // [digit][vector][coordinate]; rows of 80 bytes (5 16-byte units), so
+    // that the 16 lanes of an operand read or a staging write meet 16
+    // distinct bank groups
+    __shared__ __align__(16) int8_t Bs[4][ST][SC_LD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.y, nx = min(ST, batch - g * ST);
     const int d = 1 << k, words = d >= 32 ? d / 32 : 1;
-    {
-        uint64_t v = 0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v |= (uint64_t)(((tid >> e) & 1) ? 0xFFu : 0x01u) << (8 * e);
-        lut[tid] = v;
-    }
     // this lane's draw: row lane % 16 of the wave's block
     const int row = lane & 15;
-    const int N = J * K, JP = (J + 63) & ~63, jblocks = JP / 64;
-    const int kb = blockIdx.x / jblocks, jb0 = (blockIdx.x % jblocks) * 64 + wave * 16;
-    const int j = kb * J + jb0 + row;
+    const int N = J * K, JP = (J + 63) & ~63, jblocks = JP / SC_DRAWS;
+    const int kb = blockIdx.x / jblocks, jb0 = (blockIdx.x % jblocks) * SC_DRAWS + wave * 16;
+    const int jl = jb0 + row;
     uint32_t my_l = 0;
-    if (jb0 + row < J) {
+    if (jl < J) {
+        const int j = kb * J + jl;
         uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + g), 1, 0};
         philox4x64_10(c4, seed, 0);
         const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
         my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
     }
     const uint32_t bb = my_l >> k, ww = my_l & (uint32_t)(d - 1);
-    const bool kerdock_row = jb0 + row < J && (int)bb < d / 2;
+    const bool krow = jl < J && (int)bb < d / 2;
+    const uint32_t sbase = krow ? bb * (uint32_t)words : 0u;      // a valid sign row for every lane
     const uint32_t w16 = (ww & 1u ? 0xAAAAu : 0u) ^ (ww & 2u ? 0xCCCCu : 0u) ^ (ww & 4u ? 0xF0F0u : 0u) ^
                          (ww & 8u ? 0xFF00u : 0u);
     const int kq = (lane >> 4) * 16;                 // this lane's 16 coordinates within a step
 
-    i32x4 acc[4][4];
+    i32x4 acc[4][4];                                 // [digit][column block]
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[b][c] = i32x4{0, 0, 0, 0};
-    __syncthreads();
 
-    // the digits and sign word of step q0 + 64 are loaded while the MFMAs of
-    // step q0 run
-    const int tv_s = tid >> 2, b_s = tid & 3;
-    uint4 dg[4] = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
-                   make_uint4(0u, 0u, 0u, 0u)};
-    uint32_t wd = 0u;
-    auto fetch = [&](int q0) {
-        if (tv_s < nx) {
-            const uint4 *src =
-                reinterpret_cast<const uint4 *>(digits + ((size_t)(g * ST + tv_s) * 4 + b_s) * n_pad + q0);
+    // staging of the digits: thread (vector tv_s, digit b_s) copies 64 bytes
+    const int tv_s = tid & 63, b_s = tid >> 6;
+    const int8_t *dsrc = digits + ((size_t)(g * ST + min(tv_s, nx - 1)) * 4 + b_s) * n_pad;
+    const int steps = n_pad / 64;
+    u32x4 dg[4];
+    uint32_t wd;
+    auto fetch = [&](int st) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(dsrc + st * 64);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) dg[u] = src[u];
-        }
-        const int q = q0 + kq;
-        // coordinates past d (only when n_pad > d) meet zero digits
-        wd = (kerdock_row && (q >> 5) < words) ? signs[(size_t)bb * words + (q >> 5)] : 0u;
+        for (int u = 0; u < 4; ++u) dg[u] = src[u];
+        wd = signs[sbase + min((st * 64 + kq) >> 5, words - 1)];
     };
     fetch(0);
-    for (int q0 = 0; q0 < n_pad; q0 += 64) {
+    for (int st = 0; st < steps; ++st) {
         {
-            uint4 *dst = reinterpret_cast<uint4 *>(&Bs[b_s][tv_s][0]);
+            u32x4 *dst = reinterpret_cast<u32x4 *>(&Bs[b_s][tv_s][0]);
 #pragma unroll
             for (int u = 0; u < 4; ++u) dst[u] = dg[u];
         }
-        i32x4 a = i32x4{0, 0, 0, 0};
-        if (kerdock_row) {
-            const int q = q0 + kq;
-            const uint32_t par = __popc((uint32_t)q & ww) & 1u;
-            const uint32_t m16 = ((wd >> (q & 31)) & 0xFFFFu) ^ w16 ^ (par ? 0xFFFFu : 0u);
-            const uint64_t lo8 = lut[m16 & 0xFFu], hi8 = lut[m16 >> 8];
-            a = i32x4{(int)(uint32_t)lo8, (int)(uint32_t)(lo8 >> 32), (int)(uint32_t)hi8, (int)(uint32_t)(hi8 >> 32)};
-        }
+        const int q = st * 64 + kq;
+        // coordinates past d (only when n_pad > d) meet zero digits
+        const uint32_t par = __popc((uint32_t)q & ww) & 1u;
+        const uint32_t m16 = ((wd >> (q & 31)) & 0xFFFFu) ^ w16 ^ (par ? 0xFFFFu : 0u);
+        const bool on = krow && (q >> 5) < words;
+        const i32x4 a = on ? i32x4{sign_bytes4(m16 & 15u), sign_bytes4((m16 >> 4) & 15u),
+                                   sign_bytes4((m16 >> 8) & 15u), sign_bytes4(m16 >> 12)}
+                           : i32x4{0, 0, 0, 0};
         __syncthreads();
-        if (q0 + 64 < n_pad) fetch(q0 + 64);
+        fetch(min(st + 1, steps - 1));               // unconditional: the last step reloads its own data
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -184,12 +188,12 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
     float cv[4][4];                                  // [vector block][draw v]
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int r = 4 * (lane >> 4) + v;
-        const uint32_t l_r = __shfl(my_l, r);
-        const int jr = kb * J + jb0 + r;
+        const int rr = 4 * (lane >> 4) + v;
+        const uint32_t l_r = __shfl(my_l, rr);
+        const int jr = kb * J + jb0 + rr;
 #pragma unroll
         for (int c = 0; c < 4; ++c) cv[c][v] = 0.f;
-        if (jb0 + r >= J) continue;
+        if (jb0 + rr >= J) continue;
         const uint32_t b_r = l_r >> k, w_r = l_r & (uint32_t)(d - 1);
         const bool ident = (int)b_r == d / 2;
 #pragma unroll
@@ -575,7 +579,7 @@ int launch_shared_coef(kerdock_dtype dt, const float *X, int batch, int n, int k
                        uint64_t seed, int64_t t0, int J, int K, int8_t *digits, int2 *xscale, uint32_t *ell,
                        float *coef, uint32_t *dbg_samples, float *dbg_coef, hipStream_t s) {
     const int groups = (batch + ST - 1) / ST;
-    const long long nb = (long long)K * ((J + 63) / 64);
+    const long long nb = (long long)K * ((J + SC_DRAWS - 1) / SC_DRAWS);
     if (nb > 2147483647ll) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: too many draws");
     if (groups > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "shared form: launch too large");
     const int n_pad = shared_n_pad(n);
