@@ -296,44 +296,56 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // Global loads of stage j0 + SG_BK are issued before the MFMAs of stage
-    // j0 and land in LDS after them (one LDS buffer, register prefetch).
+    // j0 and land in LDS after them (one LDS buffer, register prefetch).  The
+    // loads are branch-free (indices clamped, values masked where they are
+    // consumed) and the draw indices are loaded one stage ahead, so that a
+    // stage's loads are in flight together.
     constexpr int PASSES = SG_BK / CPP;
     u32x4 ra[PASSES];
-    float rb[8];
+    f32x4 rb[2];
+    uint32_t lv[PASSES];
     const int bj = tid >> 3, bv = (tid & 7) * 8;     // B stage: draw bj, vectors bv .. bv + 7
+    const int ar = (tid % TPC) * E;                  // A stage: rows i0 + ar .. + E - 1
+    const bool arow_ok = i0 + ar < pitch;            // pitch is a multiple of 64
+    const size_t aoff = (size_t)(arow_ok ? i0 + ar : 0) * (size_t)(16 / E);
+    auto fetch_ell = [&](int j0) {
+#pragma unroll
+        for (int ps = 0; ps < PASSES; ++ps) lv[ps] = el[min(j0 + ps * CPP + tid / TPC, Jl - 1)];
+    };
     auto fetch = [&](int j0) {
 #pragma unroll
-        for (int ps = 0; ps < PASSES; ++ps) {
-            const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
-            const int jj = j0 + cc;
-            ra[ps] = u32x4{0u, 0u, 0u, 0u};
-            if (jj < Jl && i0 + r < pitch) {
-                const unsigned char *src =
-                    table + (size_t)el[jj] * (size_t)col_bytes + (size_t)(i0 + r) * (size_t)(16 / E);
-                ra[ps] = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src));
-            }
-        }
-        {
-            const int jj = j0 + bj;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) rb[e] = (jj < Jl && bv + e < nx) ? cf[(size_t)jj * ST + bv + e] : 0.f;
-        }
+        for (int ps = 0; ps < PASSES; ++ps)
+            ra[ps] = __builtin_nontemporal_load(
+                reinterpret_cast<const u32x4 *>(table + (size_t)lv[ps] * (size_t)col_bytes + aoff));
+        const f32x4 *src = reinterpret_cast<const f32x4 *>(cf + (size_t)min(j0 + bj, Jl - 1) * ST + bv);
+        rb[0] = src[0];
+        rb[1] = src[1];
     };
+    fetch_ell(0);
     fetch(0);
+    fetch_ell(SG_BK);
     for (int j0 = 0; j0 < Jl; j0 += SG_BK) {
 #pragma unroll
         for (int ps = 0; ps < PASSES; ++ps) {
-            const int cc = ps * CPP + tid / TPC, r = (tid % TPC) * E;
+            const int cc = ps * CPP + tid / TPC;
+            const bool ok = j0 + cc < Jl && arow_ok;
             float v[E];
             widen<DT>(ra[ps], v);
 #pragma unroll
             for (int e = 0; e < E; e += 4)
-                *reinterpret_cast<f32x4 *>(&As[cc][r + e]) = f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]};
+                *reinterpret_cast<f32x4 *>(&As[cc][ar + e]) =
+                    ok ? f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]} : f32x4{0.f, 0.f, 0.f, 0.f};
         }
+        {
+            const bool ok = j0 + bj < Jl;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[bj][bv + e] = rb[e];
+            for (int e = 0; e < 8; ++e) Bs[bj][bv + e] = (ok && bv + e < nx) ? rb[e >> 2][e & 3] : 0.f;
+        }
         __syncthreads();
-        if (j0 + SG_BK < Jl) fetch(j0 + SG_BK);
+        // unconditional (indices are clamped; the last stage reloads data it
+        // does not use), so that the waits count exactly the loads they need
+        fetch(j0 + SG_BK);
+        fetch_ell(j0 + 2 * SG_BK);
 #pragma unroll
         for (int kk = 0; kk < SG_BK; kk += 4) {
             float fa[2], fb[4];
