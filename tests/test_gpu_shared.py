@@ -25,6 +25,7 @@ SHARED_CASES = [
     (70, 300, 65, 64, 1, 30),
     (1000, 1000, 64, 130, 2, 60),
     (64, 64, 70, 4099, 1, 16),          # two slices, the second with a ragged end
+    (40, 100, 65, 4101, 2, 12),         # two batches of two ragged slices each
 ]
 
 
