@@ -305,7 +305,10 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
  * bound holds per x (the events of two vectors of one group are no longer
  * independent).  With one draw list per group the batch sums become the
  * matrix product of the gathered table columns and the coefficient block of
- * the group, which reads each drawn column once per group.  Arguments,
+ * the group, which reads each drawn column once per group (FP32 tables on
+ * the FP32 matrix cores; BF16 and FP8 tables on the BF16 matrix cores with
+ * each FP32 coefficient split exactly into three BF16 parts, so that every
+ * product is exact and only the FP32 accumulation rounds).  Arguments,
  * outputs, errors and the debug outputs are those of kerdock_sparse_apply
  * (dbg_samples row t holds its group's draws); params->chunk is ignored (the
  * batch sums are accumulated by the matrix cores), J K must stay below 2^26,
