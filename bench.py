@@ -98,13 +98,13 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
            torch.empty((B,), dtype=torch.int32, device="cuda"))
     ms = (ctypes.c_float * 4)()
     for s in range(args.warmup):
-        kd.kerdock_sparse_apply(h, X, args.eps, args.s_max, J, K, args.seed, t0=s * B, out=out)
+        kd.kerdock_sparse_apply(h, X, args.eps, args.s_max, J, K, args.seed, t0=s * B, out=out, chunk=args.chunk)
     torch.cuda.synchronize()
     kern = np.zeros(4)
     t0 = time.perf_counter()
     for s in range(args.steps):
         kd.kerdock_sparse_apply(h, X, args.eps, args.s_max, J, K, args.seed, t0=s * B, out=out,
-                                kernel_ms=ms)
+                                kernel_ms=ms, chunk=args.chunk)
         kern += np.array(ms[:4])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -151,6 +151,7 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
         "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
         "gather_GBps": gbps, "gather_frac_hbm": gbps / HBM_PEAK_GBPS,
         "gather_bytes_per_launch": gather_bytes, "shared_draws": shared, "autotuned": tuned,
+        "chunk": min(J, args.chunk or (tuned["chunk"] if tuned else min(512, max(16, -(-J // 8))))),
     }
     log("%s: J=%d K=%d  %.1f x/s  %.2f ms/step  gather %.3f ms = %.0f GB/s (%.1f%%)  recall %.4f (min %.3f)  max err %.2g"
         % (dt, J, K, r["x_per_s"], r["ms_per_step"], kern[1], gbps, 100 * gbps / HBM_PEAK_GBPS,
@@ -689,6 +690,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the numerical-section regime")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="draws per FP32 partial sum in the precision forms (0: the library's default)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the gather launch (kerdock_autotune) before timing the precision forms")
     ap.add_argument("--no-shared", dest="shared", action="store_false",
