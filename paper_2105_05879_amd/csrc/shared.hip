@@ -233,49 +233,22 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
     }
 }
 
-// 16 bytes of table entries widened to FP32
-template <int DT>
-__device__ __forceinline__ void widen(const u32x4 raw, float *v) {
-    const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
-    if constexpr (DT == KERDOCK_F32) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = __uint_as_float(w[e]);
-    } else if constexpr (DT == KERDOCK_BF16) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            v[2 * e] = __uint_as_float(w[e] << 16);
-            v[2 * e + 1] = __uint_as_float(w[e] & 0xFFFF0000u);
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], false);
-            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[e], true);
-            v[4 * e + 0] = lo[0];
-            v[4 * e + 1] = lo[1];
-            v[4 * e + 2] = hi[0];
-            v[4 * e + 3] = hi[1];
-        }
-    }
-}
-
 // Draws of a batch are split into `splits` consecutive slices (a function of
 // J alone, so results never depend on the batch size), each summed by its
 // own workgroups; the slices are added in order with the batch mean.
 int shared_splits(int J) { return J / 2048 < 1 ? 1 : J / 2048 > 16 ? 16 : J / 2048; }
 
-// k_shared_gemm: grid (ceil(pitch / 128), K splits, groups), 256 threads.
-// Rows i0 .. i0 + 127 of slice sp of Y_k for the (up to) 64 vectors of
-// group g: partial[t][k][sp][i] = sum_{j in slice} T[ell[g][k J + j]][i]
-// coef[g][k J + j][t mod 64].  Wave w owns rows i0 + 32 w .. + 31, all 64 vectors:
-// 2 x 4 MFMA blocks.
-template <int DT>
+// k_shared_gemm: the product for FP32 tables.  Grid (ceil(pitch / 128), K
+// splits, groups), 256 threads.  Rows i0 .. i0 + 127 of slice sp of Y_k for
+// the (up to) 64 vectors of group g: partial[t][k][sp][i] = sum_{j in slice}
+// T[ell[g][k J + j]][i] coef[g][k J + j][t mod 64].  Wave w owns rows
+// i0 + 32 w .. + 31, all 64 vectors: 2 x 4 MFMA blocks.
 __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__restrict__ table, int col_bytes, int pitch,
                                                      int batch, int J, int K, int N, int splits,
                                                      const uint32_t *__restrict__ ell,
                                                      const float *__restrict__ coef,
                                                      float *__restrict__ partial) {
-    constexpr int E = Elems<DT>::N;           // entries per 16 bytes
+    constexpr int E = 4;                      // FP32 entries per 16 bytes
     constexpr int TPC = SG_BM / E;            // threads per column slice
     constexpr int CPP = 256 / TPC;            // column slices per pass
     static_assert(SG_BK % CPP == 0, "whole passes");
@@ -329,12 +302,10 @@ __global__ __launch_bounds__(256) void k_shared_gemm(const unsigned char *__rest
         for (int ps = 0; ps < PASSES; ++ps) {
             const int cc = ps * CPP + tid / TPC;
             const bool ok = j0 + cc < Jl && arow_ok;
-            float v[E];
-            widen<DT>(ra[ps], v);
-#pragma unroll
-            for (int e = 0; e < E; e += 4)
-                *reinterpret_cast<f32x4 *>(&As[cc][ar + e]) =
-                    ok ? f32x4{v[e], v[e + 1], v[e + 2], v[e + 3]} : f32x4{0.f, 0.f, 0.f, 0.f};
+            *reinterpret_cast<f32x4 *>(&As[cc][ar]) =
+                ok ? f32x4{__uint_as_float(ra[ps].x), __uint_as_float(ra[ps].y), __uint_as_float(ra[ps].z),
+                           __uint_as_float(ra[ps].w)}
+                   : f32x4{0.f, 0.f, 0.f, 0.f};
         }
         {
             const bool ok = j0 + bj < Jl;
@@ -615,7 +586,7 @@ int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch
     const int cb = pitch * (int)dtype_bytes(dt), N = J * K;
     switch (dt) {
     case KERDOCK_F32:
-        hipLaunchKernelGGL(k_shared_gemm<KERDOCK_F32>, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
+        hipLaunchKernelGGL(k_shared_gemm, grid, dim3(256), 0, s, tb, cb, pitch, batch, J, K, N, splits, ell,
                            coef, partial);
         break;
     case KERDOCK_BF16:
