@@ -40,7 +40,8 @@ constexpr int SG_BK = 32;                     // draws per LDS stage
 // Identity draws (basis d/2) give sqrt(d) x[w] directly.
 
 // k_x_digits: grid (batch), one wave.  digits[t][b][q] (q < n_pad, zero
-// beyond n) and the scale exponent / finiteness of x_t.
+// beyond n) and xscale[t] = (scale exponent, flags): bit 0 x_t is finite,
+// bit 1 its top digit plane (b = 3) has a nonzero digit.
 template <int P>
 __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, int n, int n_pad,
                                                  int8_t *__restrict__ digits, int2 *__restrict__ xscale) {
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
     bool finite;
     fixed_point<P>(X + (size_t)t * n, n, lane, xi, E2, finite);
     int8_t *dt = digits + (size_t)t * 4 * n_pad;
+    uint32_t top = 0u;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int e0 = (lane + 64 * p) * 32;
@@ -72,8 +74,11 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
 #pragma unroll
             for (int w = 0; w < 8; ++w) dst[w] = packed[b][w];
         }
+#pragma unroll
+        for (int w = 0; w < 8; ++w) top |= packed[3][w];
     }
-    if (lane == 0) xscale[t] = make_int2(E2, finite ? 1 : 0);
+    const bool top_any = __ballot(top != 0u) != 0;
+    if (lane == 0) xscale[t] = make_int2(E2, (finite ? 1 : 0) | (top_any ? 2 : 0));
 }
 
 typedef int i32x4 __attribute__((ext_vector_type(4)));
@@ -143,21 +148,30 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[b][c] = i32x4{0, 0, 0, 0};
 
+    // The top digit plane is skipped for a group whose vectors all have it
+    // zero (typical for unit vectors: it only holds entries beyond about
+    // 2^23 of the fixed-point scale); its products would all be zero.
+    const bool top = __syncthreads_or(tid < nx && (xscale[g * ST + tid].y & 2)) != 0;
     // staging of the digits: thread (vector tv_s, digit b_s) copies 64 bytes
     const int tv_s = tid & 63, b_s = tid >> 6;
+    const bool stage = b_s < 3 || top;              // uniform per wave
     const int8_t *dsrc = digits + ((size_t)(g * ST + min(tv_s, nx - 1)) * 4 + b_s) * n_pad;
     const int steps = n_pad / 64;
     u32x4 dg[4];
     uint32_t wd;
+    // digits of step st for the LDS tile (waves that stage), and the sign
+    // word of this lane's draw (every wave)
     auto fetch = [&](int st) {
-        const u32x4 *src = reinterpret_cast<const u32x4 *>(dsrc + st * 64);
+        if (stage) {
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(dsrc + st * 64);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dg[u] = src[u];
+            for (int u = 0; u < 4; ++u) dg[u] = src[u];
+        }
         wd = signs[sbase + min((st * 64 + kq) >> 5, words - 1)];
     };
     fetch(0);
     for (int st = 0; st < steps; ++st) {
-        {
+        if (stage) {
             u32x4 *dst = reinterpret_cast<u32x4 *>(&Bs[b_s][tv_s][0]);
 #pragma unroll
             for (int u = 0; u < 4; ++u) dst[u] = dg[u];
@@ -171,11 +185,12 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                    sign_bytes4((m16 >> 8) & 15u), sign_bytes4(m16 >> 12)}
                            : i32x4{0, 0, 0, 0};
         __syncthreads();
-        fetch(min(st + 1, steps - 1));               // unconditional: the last step reloads its own data
+        fetch(min(st + 1, steps - 1));               // the last step reloads its own data
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
+                if (b == 3 && !top) continue;        // uniform
                 const i32x4 bop = *reinterpret_cast<const i32x4 *>(&Bs[b][c * 16 + row][kq]);
                 acc[b][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bop, acc[b][c], 0, 0, 0);
             }
@@ -208,7 +223,7 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                 const int2 sc = xscale[t];
                 const int64_t tot = (int64_t)acc[0][c][v] + ((int64_t)acc[1][c][v] << 8) +
                                     ((int64_t)acc[2][c][v] << 16) + ((int64_t)acc[3][c][v] << 24);
-                cf = sc.y ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
+                cf = (sc.y & 1) ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
             }
             cv[c][v] = cf;
             if (!by_vector) coef[((size_t)g * N + jr) * ST + tv] = cf;

@@ -61,6 +61,38 @@ def test_shared_parity(orc, m, n, B, J, K, s_max, dtype):
     assert exc <= 1
 
 
+def test_shared_top_digit_plane(orc):
+    """Coefficients are exact sums over four base-256 digit planes of the
+    fixed-point x; a group whose vectors all have a zero top plane skips it.
+    The top plane is nonzero when an entry exceeds about 2^-7 of the vector's
+    l1 norm.  Group 0 holds dense unit vectors of n = 1024 (entries near
+    2^-8 of the l1 norm at most: top plane zero), group 1 adds a near one-hot
+    vector (top plane nonzero): both paths in one call, against the oracle."""
+    kd = need_gpu()
+    m, n, B, J, K, s_max = 64, 1024, 128, 40, 2, 12
+    A = rand_A(m, n, 91)
+    X = unit_rows(B, n, 92)
+    spike = np.zeros(n, dtype=np.float64)
+    spike[5] = 1.0
+    spike += 1e-3 * np.random.default_rng(93).standard_normal(n)
+    X[70] = (spike / np.linalg.norm(spike)).astype(np.float32)
+    A64, X64 = A.astype(np.float64), X.astype(np.float64)
+    eps = float(np.quantile(np.abs(X64 @ A64.T), 0.9)) + 1e-6
+    for dtype in ("f32", "bf16"):
+        h = kd.kerdock_prepare(torch.from_numpy(A).cuda(), dtype)
+        idx, val, cnt, dbg = kd.kerdock_sparse_apply_shared(h, torch.from_numpy(X).cuda(), eps, s_max, J, K, 515,
+                                                            debug=True)
+        torch.cuda.synchronize()
+        g = {key: v.cpu().numpy() for key, v in dbg.items()}
+        g.update(idx=idx.cpu().numpy(), val=val.cpu().numpy(), cnt=cnt.cpu().numpy())
+        mode = {"f32": "exact", "bf16": "bf16"}[dtype]
+        r = orc.sparse_apply(A64, X64, J, K, eps, s_max, seed=515, table_mode=mode, debug=True, tile=TILE)
+        info = h.info
+        h.destroy()
+        assert check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, chunk=J,
+                          terms=shared_terms(J, dtype)) <= 1
+
+
 def test_shared_groups_follow_stream_position(orc):
     """A batch of 128 equals two calls of 64 rows at t0 and t0 + 1."""
     kd = need_gpu()
