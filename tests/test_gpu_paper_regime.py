@@ -8,6 +8,9 @@ must return exactly the 20 planted rows with their values (h_eps with eps
 half the planted magnitude keeps them and drops the FP32 rounding noise of
 the other rows), up to a few vectors on which the FP64 oracle, given the
 same draws, fails as well."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,10 +20,15 @@ from paper_2105_05879_amd import workloads
 
 pytestmark = pytest.mark.gpu
 
+# the experiment's printed parameters (tests/golden/numerical_section.json)
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "numerical_section.json")))
+J, K = GOLDEN["J"], GOLDEN["K"]
+S_MAX = GOLDEN["rows_kept_per_unit_sparsity"] * GOLDEN["s"]
+
 
 @pytest.fixture(scope="module")
 def regime():
-    return workloads.paper_regime(batch=1000)
+    return workloads.paper_regime(batch=GOLDEN["trials"], n=GOLDEN["n"], s=GOLDEN["s"])
 
 
 def recovery_failures(w, idx, val, cnt):
@@ -41,7 +49,7 @@ def confirm_with_oracle(orc, w, t, dtype, seed, t0, tile):
     failure is the estimator's (a draw list whose median of means strays),
     not the kernels'."""
     mode = {"f32": "exact", "bf16": "bf16"}[dtype]
-    r = orc.sparse_apply(w.A.astype(np.float64), w.X[t:t + 1].astype(np.float64), 375, 2, w.eps, 200,
+    r = orc.sparse_apply(w.A.astype(np.float64), w.X[t:t + 1].astype(np.float64), J, K, w.eps, S_MAX,
                          seed=seed, t0=t0, table_mode=mode, tile=tile)
     got = r["out_idx"][0][:r["out_cnt"][0]]
     assert not np.array_equal(got, w.supports[t]), "oracle recovers vector %d, the GPU does not" % t
@@ -59,7 +67,7 @@ def test_exact_recovery_in_1000_trials(orc, regime, dtype):
     w = regime
     h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
     X = torch.from_numpy(w.X).cuda()
-    idx, val, cnt = kd.kerdock_sparse_apply(h, X, w.eps, 200, 375, 2, seed=2021)
+    idx, val, cnt = kd.kerdock_sparse_apply(h, X, w.eps, S_MAX, J, K, seed=2021)
     torch.cuda.synchronize()
     h.destroy()
     bad = recovery_failures(w, idx.cpu().numpy(), val.cpu().numpy(), cnt.cpu().numpy())
@@ -76,7 +84,7 @@ def test_exact_recovery_shared_draws(orc, regime, dtype):
     w = regime
     h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
     X = torch.from_numpy(w.X).cuda()
-    idx, val, cnt = kd.kerdock_sparse_apply_shared(h, X, w.eps, 200, 375, 2, 2021)
+    idx, val, cnt = kd.kerdock_sparse_apply_shared(h, X, w.eps, S_MAX, J, K, 2021)
     torch.cuda.synchronize()
     h.destroy()
     bad = recovery_failures(w, idx.cpu().numpy(), val.cpu().numpy(), cnt.cpu().numpy())

@@ -48,6 +48,22 @@ def test_theory_params_match_theorem5(near):
     h.destroy()
 
 
+def test_theory_K_near_eta_one_at_n_4096():
+    """The numerical section remarks that eta = 1 already gives a lower bound
+    on K above 16 at n = 4096 (tests/golden/numerical_section.json); the
+    entry point takes eta < 1, and just below 1 it returns that K."""
+    import json
+    import os
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "numerical_section.json")))
+    kd = need_gpu()
+    A = np.random.default_rng(8).standard_normal((golden["n"], 16)).astype(np.float32)
+    h = kd.kerdock_prepare(torch.from_numpy(A).cuda(), "bf16")
+    _, K, _, _ = kd.kerdock_theory_params(h, 0.5, 0.0, 1.0 - 1e-6)
+    h.destroy()
+    assert K == math.ceil(2 * math.log(golden["n"])) == 17
+    assert K > golden["theorem5_K_lower_bound_at_eta_1_exceeds"]
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_failure_rate_at_most_eta(near, dtype):
     kd = need_gpu()
