@@ -106,8 +106,9 @@ __device__ __forceinline__ int sign_bytes4(uint32_t m) {
 // bitmaps and the Walsh pattern of w, sixteen coordinates (one 128-bit
 // operand) per lane; A and B give every lane the same 16 consecutive
 // coordinates of the step.  The next step's digits and sign word are loaded
-// before this step's MFMAs, with clamped indices and no branches, so that no
-// wait covers more than the loads it needs.
+// before this step's MFMAs, with clamped indices (the only branch is the
+// wave-uniform skip of a zero top digit plane), so that no wait covers more
+// than the loads it needs.
 __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
                                                      const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
                                                      int batch, int J, int K, int by_vector,
