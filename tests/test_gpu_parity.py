@@ -300,21 +300,26 @@ def test_errors(orc):
     h.destroy()
 
 
-def test_non_finite_input_is_flagged(orc):
+@pytest.mark.parametrize("shared", [False, True])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_non_finite_input_is_flagged(orc, shared, dtype):
     """An inf or NaN in x makes the survivor values non-finite: count -1 and
-    all-padding rows for that vector, the other vectors unaffected."""
+    all-padding rows for that vector, the other vectors unaffected (in the
+    shared-draw form too, where all four vectors are one group and a vector
+    alone at t0 = 0 uses the same draws)."""
     kd = need_gpu()
     A = rand_A(64, 64, 7)
     Xn = unit_rows(4, 64, 8)
     Xn[1, 5] = np.nan
     Xn[2, 9] = np.inf
-    h = prepare(kd, A, "f32")
-    idx, val, cnt = kd.kerdock_sparse_apply(h, torch.from_numpy(Xn).cuda(), 0.05, 8, 40, 2, 11, t0=0)
+    h = prepare(kd, A, dtype)
+    fn = kd.kerdock_sparse_apply_shared if shared else kd.kerdock_sparse_apply
+    idx, val, cnt = fn(h, torch.from_numpy(Xn).cuda(), 0.05, 8, 40, 2, 11, t0=0)
     torch.cuda.synchronize()
     assert cnt[1].item() == -1 and cnt[2].item() == -1
     assert torch.all(idx[1:3] == -1) and torch.all(val[1:3] == 0)
     for t in (0, 3):
-        ref = kd.kerdock_sparse_apply(h, torch.from_numpy(Xn[t:t + 1]).cuda(), 0.05, 8, 40, 2, 11, t0=t)
+        ref = fn(h, torch.from_numpy(Xn[t:t + 1]).cuda(), 0.05, 8, 40, 2, 11, t0=0 if shared else t)
         assert torch.equal(ref[0][0], idx[t]) and torch.equal(ref[1][0], val[t]) and ref[2][0].item() == cnt[t].item()
         assert cnt[t].item() >= 0
     h.destroy()
