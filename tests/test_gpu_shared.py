@@ -26,6 +26,7 @@ SHARED_CASES = [
     (1000, 1000, 64, 130, 2, 60),
     (64, 64, 70, 4099, 1, 16),          # two slices, the second with a ragged end
     (40, 100, 65, 4101, 2, 12),         # two batches of two ragged slices each
+    (50, 50, 66, 21, 5, 10),            # five batches: median of five means
 ]
 
 
