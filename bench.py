@@ -151,7 +151,8 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
         "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
         "gather_GBps": gbps, "gather_frac_hbm": gbps / HBM_PEAK_GBPS,
         "gather_bytes_per_launch": gather_bytes, "shared_draws": shared, "autotuned": tuned,
-        "chunk": min(J, args.chunk or (tuned["chunk"] if tuned else min(512, max(16, -(-J // 8))))),
+        "chunk": min(J, args.chunk or (tuned["chunk"] if tuned else
+                                       min(768 if dt == "fp8" else 512, max(16, -(-J // 8))))),
     }
     log("%s: J=%d K=%d  %.1f x/s  %.2f ms/step  gather %.3f ms = %.0f GB/s (%.1f%%)  recall %.4f (min %.3f)  max err %.2g"
         % (dt, J, K, r["x_per_s"], r["ms_per_step"], kern[1], gbps, 100 * gbps / HBM_PEAK_GBPS,

@@ -92,9 +92,9 @@ typedef struct {
     /* draws per FP32 partial sum of a batch mean.  The exact rounding of mu
        depends on this and on nothing else about the launch (batch size,
        workgroup shape and unroll leave it unchanged): 0 = the value that
-       kerdock_autotune stored in the handle, else min(512, max(16,
-       ceil(J / 8))); 1..1024 = that many (capped at J); other values are
-       INVALID_ARG. */
+       kerdock_autotune stored in the handle, else min(C, max(16,
+       ceil(J / 8))) with C = 768 for FP8 tables and 512 otherwise;
+       1..1024 = that many (capped at J); other values are INVALID_ARG. */
     int32_t chunk;
 } kerdock_apply_params;
 

@@ -63,12 +63,14 @@ static int env_int(const char *name, int dflt) {
 
 // Draws per FP32 partial sum: the caller's value, else the tuned one, else
 // about J/8 (so that a single vector still spreads over several chunks per
-// batch) between 16 and 512; never above J.
+// batch) between 16 and 512, or 768 for FP8 tables (whose 2-byte-per-row
+// columns are short, so a workgroup's coefficient work is amortised over
+// more draws); never above J.
 int chunk_for(const kerdock_handle_s *h, int J, int requested) {
     int c;
     if (requested > 0) c = requested;
     else if (h->tune_chunk > 0) c = h->tune_chunk;
-    else c = std::min(512, std::max(16, (J + 7) / 8));
+    else c = std::min(h->dtype == KERDOCK_FP8E4M3 ? 768 : 512, std::max(16, (J + 7) / 8));
     c = std::min(c, gather_chunk_max());
     return c < J ? c : J;
 }

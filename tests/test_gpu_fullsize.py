@@ -76,7 +76,7 @@ def test_fullsize(orc, wl, dtype):
         rows = np.unique(np.concatenate([g["survivors"][t][:8], rng.integers(0, 2048, 8)]))
         ent = orc.table_entries(A64, ls, rows)                          # (N, R)
         tolE, used = entry_tolerance(orc, ent, A64[rows], info.k, info.d, dtype)
-        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), 512)
+        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), 768 if dtype == "fp8" else 512)
         mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
         dmu = np.abs(g["mu"][t][rows] - mu_o)
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
