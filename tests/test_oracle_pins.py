@@ -541,3 +541,93 @@ def test_invalid_arguments(orc):
                dict(J=1, K=1, eps=0.1, s_max=65)]:
         with pytest.raises(ValueError):
             orc.sparse_apply(w.A, w.X, seed=0, **kw)
+
+
+# ------------------------------------- the oracle's full-size checkers ---
+# ko_sign_words, ko_table_entries and ko_mu_rows serve as expected values of
+# the GPU parity tests at sizes where ko_sparse_apply is too slow; each is
+# pinned here to an independent computation of the same definition.
+
+def _quadratic_form_bits(M, d):
+    """Q_M(x) = sum_{i<j} M_ij x_i x_j mod 2 for every x < d, by numpy
+    (equation (3)), independent of the oracle's scalar routine."""
+    k = M.shape[0]
+    x = np.arange(d, dtype=np.int64)
+    bits = ((x[:, None] >> np.arange(k)[None, :]) & 1).astype(np.int64)       # (d, k)
+    upper = np.triu(M.astype(np.int64), 1)
+    return ((bits @ upper) * bits).sum(1) & 1
+
+
+def _unpack_words(words, d):
+    return ((words[np.arange(d) // 32] >> (np.arange(d) % 32).astype(np.uint32)) & 1).astype(np.int64)
+
+
+@pytest.mark.parametrize("k", [2, 4, 6, 8])
+def test_sign_words_are_the_quadratic_form_every_basis(orc, k):
+    d = 1 << k
+    for s in range(d // 2):
+        M = orc.kerdock_matrix(k, s)
+        want = _quadratic_form_bits(M, d)
+        assert np.array_equal(_unpack_words(orc.sign_words(k, s), d), want), s
+        # and the oracle's scalar routine agrees on a few points
+        for x in (0, 1, d - 1, d // 3):
+            assert orc.quadratic_form(M, x) == want[x]
+
+
+def test_sign_words_are_the_quadratic_form_sampled_k12(orc):
+    k, d = 12, 4096
+    for s in [0, 1, 2, 1000, 1365, 2047] + list(np.random.default_rng(12).integers(0, 2048, 6)):
+        M = orc.kerdock_matrix(k, int(s))
+        assert np.array_equal(_unpack_words(orc.sign_words(k, int(s)), d), _quadratic_form_bits(M, d)), s
+
+
+@pytest.mark.parametrize("m,n", [(7, 16), (30, 50), (64, 64)])
+def test_table_entries_equal_the_full_table(orc, m, n):
+    """T[l_j]_r for random draws (Kerdock and identity blocks, zero columns
+    included) and random rows, against the full sketch ko_table (itself
+    pinned by equation (1) above) and against numpy's product of the design
+    vectors with A."""
+    rng = np.random.default_rng(m * n)
+    A = rng.standard_normal((m, n))
+    k = orc.choose_k(n)
+    d, L = 1 << k, orc.design_size(k)
+    T = orc.table(A)
+    ls = np.concatenate([rng.integers(0, L, 40), [0, L - 1, (d // 2) * d, (d // 2) * d + n - 1]])
+    if n < d:
+        ls = np.concatenate([ls, [(d // 2) * d + n]])
+    rows = np.unique(np.concatenate([rng.integers(0, m, 5), [0, m - 1]]))
+    got = orc.table_entries(A, ls, rows)
+    assert np.allclose(got, T[ls][:, rows], rtol=0, atol=1e-12)
+    S = np.stack([orc.design_vector(n, k, int(l)) for l in ls])
+    assert np.allclose(got, S @ A[rows].T, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("table_mode", ["exact", "bf16", "fp8"])
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_mu_rows_equals_the_pipeline(orc, table_mode, K):
+    """The row-restricted median of means on every row, for given draws,
+    equals both ko_sparse_apply's debug mu and the numpy re-computation of
+    the streaming steps (batch slices, median, FP8 row scale).  A
+    rectangular A with n not a power of 4 catches a wrong dimension."""
+    rng = np.random.default_rng(40 + K)
+    m, n, J = 37, 50, 7
+    A = rng.standard_normal((m, n))
+    X = rng.standard_normal((2, n))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    r = orc.sparse_apply(A, X, J, K, 0.1, 9, seed=77, t0=3, table_mode=table_mode, debug=True)
+    d = 1 << orc.choose_k(n)
+    scale = np.maximum(np.abs(A).sum(1), np.sqrt(d) * np.abs(A).max(1)) / 448.0
+    scale = scale.astype(np.float32).astype(np.float64)
+    fn = {"exact": lambda l: orc.table_column(A, l),
+          "bf16": lambda l: orc.quant_bf16(orc.table_column(A, l)),
+          "fp8": lambda l: scale * orc.quant_e4m3(orc.table_column(A, l) / scale)}[table_mode]
+    rows = np.arange(m)
+    for t in range(2):
+        ls = r["samples"][t]
+        mu = orc.mu_rows(A, X[t], ls, J, K, rows, table_mode)
+        assert np.allclose(mu, r["mu"][t], rtol=0, atol=1e-12)
+        _, _, mu_np, _, _, _ = _pipeline_by_numpy(orc, A, X[t], J, K, 9, 0.1, ls, fn)
+        assert np.allclose(mu, mu_np, rtol=0, atol=1e-12)
+        # a subset of rows in any order gives the same values
+        sub = rng.permutation(m)[:5]
+        assert np.allclose(orc.mu_rows(A, X[t], ls, J, K, sub, table_mode), mu[sub], rtol=0, atol=0)
