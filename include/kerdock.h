@@ -288,8 +288,10 @@ int kerdock_learned_attach(kerdock_handle h, kerdock_mlp net);
  * of h_eps(Ax) outside C removes at least eps^2 from the verified energy, so
  * no such row is accepted without the fallback).  fallback (device [B]
  * int32) receives 1 for the recomputed rows.  Outputs as in
- * kerdock_sparse_apply.  Errors: NOT_PREPARED (no attached network),
- * INVALID_ARG, OOM, HIP.
+ * kerdock_sparse_apply.  Debug: when p->dbg_survivors is given it receives
+ * the candidate set C of every row ([B][s_max], ascending, padded with -1);
+ * the other debug fields and kernel_ms are ignored.  Errors: NOT_PREPARED
+ * (no attached network), INVALID_ARG, OOM, HIP.
  */
 int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, int s_max,
                           const kerdock_apply_params *p, int32_t *out_idx, float *out_val,

@@ -54,6 +54,7 @@ def _load():
         "ko_draw_samples_stream": (None, [c_u64, c_i64, c_u64, c_i64, c_i64, c_p]),
         "ko_quant_bf16": (c_d, [c_d]),
         "ko_quant_e4m3": (c_d, [c_d]),
+        "ko_quant_array": (None, [c_p, c_i64, c_i]),
         "ko_sign_words": (None, [c_i, c_u64, c_p]),
         "ko_table_entries": (None, [c_p, c_i, c_i, c_p, c_i64, c_p, c_i, c_p]),
         "ko_mu_rows": (None, [c_p, c_i, c_i, c_p, c_p, c_i, c_i, c_p, c_i, c_i, c_p]),
@@ -152,14 +153,20 @@ def draw_samples(seed, t, N, L, stream=None):
     return out
 
 
+def _quant(x, mode):
+    a = np.array(x, dtype=np.float64, copy=True, order="C")
+    _load().ko_quant_array(_ptr(a), a.size, mode)
+    return a if a.ndim else float(a)
+
+
 def quant_bf16(x):
-    f = _load().ko_quant_bf16
-    return np.vectorize(lambda v: f(float(v)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+    """Round to bfloat16 (nearest, ties to even), elementwise."""
+    return _quant(x, 1)
 
 
 def quant_e4m3(x):
-    f = _load().ko_quant_e4m3
-    return np.vectorize(lambda v: f(float(v)), otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+    """Round to OCP FP8 E4M3 (nearest, ties to even, saturating at 448), elementwise."""
+    return _quant(x, 2)
 
 
 def sign_words(k, s):

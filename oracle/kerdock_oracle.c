@@ -346,6 +346,14 @@ double ko_quant_e4m3(double x)
     return x < 0 ? -r : r;
 }
 
+/* the two quantisers applied elementwise to an array (in place) */
+void ko_quant_array(double *x, int64_t count, int mode)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < count; i++)
+        x[i] = mode == 1 ? ko_quant_bf16(x[i]) : ko_quant_e4m3(x[i]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Algorithm 1, streaming step, with Theorem 5's median of means.            */
 /* ------------------------------------------------------------------------ */

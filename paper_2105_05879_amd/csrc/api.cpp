@@ -356,7 +356,13 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
     h->L = (int64_t)h->d * (h->d / 2 + 1);
     h->pitch = column_pitch(m);
     h->dtype = dtype;
-    KD_HIP(hipGetDevice(&h->device));
+    {
+        hipError_t e0 = hipGetDevice(&h->device);
+        if (e0 != hipSuccess) {
+            delete h;
+            return hip_fail(e0, "hipGetDevice");
+        }
+    }
 
     std::vector<uint16_t> masks = kerdock_masks(h->k, &h->poly);
     const size_t nb = (size_t)h->d / 2;
@@ -364,7 +370,13 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
     h->table_bytes = (size_t)h->L * h->pitch * dtype_bytes(dtype);
 
     size_t free_b = 0, total_b = 0;
-    KD_HIP(hipMemGetInfo(&free_b, &total_b));
+    {
+        hipError_t e0 = hipMemGetInfo(&free_b, &total_b);
+        if (e0 != hipSuccess) {
+            delete h;
+            return hip_fail(e0, "hipMemGetInfo");
+        }
+    }
     const size_t side = (size_t)m * n * 4 + nb * wpb * 4 + masks.size() * 2 + (size_t)h->pitch * 4;
     if (h->table_bytes + side + ((size_t)1 << 28) > free_b) {
         const std::string msg = "table of " + std::to_string(h->table_bytes) + " bytes does not fit in free device memory";

@@ -226,6 +226,7 @@ int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int 
     const GatherShape g = gather_shape(dt, a.pitch, (long long)batch * K * a.chunks_per_batch);
     // a launch too small to fill the chip is latency-bound: most loads in flight
     if (g.small) unroll = 16;
+    if (batch > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "batch above 65535 (grid z dimension of the gather)");
     dim3 grid(K * a.chunks_per_batch, g.segs, batch);
     switch (dt) {
     case KERDOCK_F32: launch_dt<KERDOCK_F32>(grid, g, unroll, a, s); break;

@@ -366,8 +366,21 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
         rc = gemm_f32(false, false, X, h->n, L->Gram, h->n, B, h->n, h->n, nullptr, h->n, X, rowpart, s);
     if (rc == KERDOCK_OK) rc = launch_rowsum(rowpart, B, parts, E, s);
     if (rc == KERDOCK_OK) rc = launch_fallback_flags(E, vs2, B, 0.5f * eps * eps, fallback, s);
-    // fallback: the plain streaming step on the flagged rows only
-    if (rc == KERDOCK_OK) rc = apply_internal(h, X, B, eps, s_max, p, out_idx, out_val, out_cnt, fallback, stream);
+    // debug: the candidate set C of every row (ascending, padded with -1)
+    if (rc == KERDOCK_OK && p->dbg_survivors) {
+        hipError_t e = hipMemcpyAsync(p->dbg_survivors, cand, (size_t)B * s_max * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = hip_fail(e, "candidate dump");
+    }
+    // fallback: the plain streaming step on the flagged rows only (its own
+    // debug dumps are not requested)
+    kerdock_apply_params pf = *p;
+    pf.dbg_samples = nullptr;
+    pf.dbg_coef = nullptr;
+    pf.dbg_mu = nullptr;
+    pf.dbg_survivors = nullptr;
+    pf.dbg_values = nullptr;
+    pf.kernel_ms = nullptr;
+    if (rc == KERDOCK_OK) rc = apply_internal(h, X, B, eps, s_max, &pf, out_idx, out_val, out_cnt, fallback, stream);
     return rc;
 }
 

@@ -296,6 +296,11 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         chunk[q] = chunk_for(h, J, params[q].chunk);
         cpb[q] = (J + chunk[q] - 1) / chunk[q];
         nchunks[q] = K * cpb[q];
+        if (nchunks[q] > 0xFFFFFF) {       // the chunk id of a work item has 24 bits
+            delete pl;
+            return fail(KERDOCK_ERR_INVALID_ARG, "multi: K ceil(J / chunk) must stay below 2^24 for handle " +
+                                                     std::to_string(q));
+        }
         const GatherShape gs = gather_shape(h->dtype, h->pitch);
         grouped[q] = gs.grouped;
         pl->tiles = std::max(pl->tiles, gs.tiles);

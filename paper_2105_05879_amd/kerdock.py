@@ -147,6 +147,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _check_x(X, n, name="X"):
+    """X must be a (B, n) FP32 CUDA tensor: the kernels read B n floats."""
+    _dev(X, torch.float32, name)
+    if X.dim() != 2 or X.shape[1] != n:
+        raise ValueError("%s must have shape (batch, %d), got %s" % (name, n, tuple(X.shape)))
+
+
+def _check_out(out, B, s_max, device):
+    """Caller-supplied outputs: idx (B, s_max) int32, val (B, s_max) FP32,
+    cnt (B,) int32, contiguous, on X's device."""
+    if len(out) != 3:
+        raise ValueError("out must be (idx, val, cnt)")
+    for t, dt, shp, name in zip(out, (torch.int32, torch.float32, torch.int32),
+                                ((B, s_max), (B, s_max), (B,)), ("idx", "val", "cnt")):
+        _dev(t, dt, name)
+        if tuple(t.shape) != shp or t.device != device:
+            raise ValueError("%s must have shape %s on %s, got %s on %s" % (name, shp, device, tuple(t.shape),
+                                                                           t.device))
+
+
 class Handle:
     """A prepared matrix: owns the device tables until destroyed."""
 
@@ -201,12 +221,14 @@ def kerdock_reserve(h, batch, J, K, s_max):
 
 def _sparse_apply(entry, h, X, eps, s_max, J, K, seed, t0, tau, out, debug, stream, kernel_ms, chunk):
     """Shared body of the two streaming entry points."""
+    _check_x(X, h.n)
     B = X.shape[0]
     dev = X.device
     if out is None:
         out = (torch.empty((B, s_max), dtype=torch.int32, device=dev),
                torch.empty((B, s_max), dtype=torch.float32, device=dev),
                torch.empty((B,), dtype=torch.int32, device=dev))
+    _check_out(out, B, s_max, dev)
     idx, val, cnt = out
     p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau, chunk=chunk)
     if kernel_ms is not None:          # a ctypes c_float * 4 filled by the call
@@ -256,7 +278,9 @@ def kerdock_sparse_apply_shared(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out
 
 def kerdock_read_columns(h, ells, stream=None):
     """Dequantised table columns T[l] (times the FP8 row scale), [count, m]."""
-    ells = ells.to(torch.int32).contiguous()
+    if not (isinstance(ells, torch.Tensor) and ells.is_cuda):
+        raise TypeError("ells must be a CUDA tensor")
+    ells = ells.to(torch.int32).contiguous().view(-1)
     out = torch.empty((ells.numel(), h.m), dtype=torch.float32, device=ells.device)
     _check(lib().kerdock_read_columns(h.ptr, _ptr(ells), ells.numel(), _ptr(out), _stream(stream)))
     return out
@@ -278,6 +302,7 @@ def kerdock_row_scales(h, stream=None):
 def kerdock_autotune(h, X, J, K, stream=None):
     """Time the gather shapes on X and keep the fastest in the handle.
     Returns (chunk, unroll, ms)."""
+    _check_x(X, h.n)
     c, u, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
     _check(lib().kerdock_autotune(h.ptr, _dev(X, torch.float32, "X"), X.shape[0], J, K, _stream(stream),
                                   ctypes.byref(c), ctypes.byref(u), ctypes.byref(ms)))
@@ -312,6 +337,13 @@ class MultiPlan:
 
 def _multi_args(handles, Xs, params, s_max, outs):
     nh = len(handles)
+    if not (len(Xs) == nh and len(params) == nh and len(s_max) == nh and (outs is None or len(outs) == nh)):
+        raise ValueError("handles, Xs, params, s_max (and outs) must have one entry per handle")
+    for h, X in zip(handles, Xs):
+        _check_x(X, h.n)
+    if outs is not None:
+        for X, sm, o in zip(Xs, s_max, outs):
+            _check_out(o, X.shape[0], sm, X.device)
     if outs is None:
         outs = [(torch.empty((X.shape[0], sm), dtype=torch.int32, device=X.device),
                  torch.empty((X.shape[0], sm), dtype=torch.float32, device=X.device),
@@ -415,6 +447,7 @@ def kerdock_mlp_set_params(net, params):
 
 
 def kerdock_mlp_forward(net, F, stream=None):
+    _check_x(F, net.dims[0], "F")
     Z = torch.empty((F.shape[0], net.dims[3]), dtype=torch.float32, device=F.device)
     _check(lib().kerdock_mlp_forward(net.ptr, _dev(F, torch.float32, "F"), F.shape[0], _ptr(Z), _stream(stream)))
     return Z
@@ -422,6 +455,9 @@ def kerdock_mlp_forward(net, F, stream=None):
 
 def kerdock_mlp_train_step(net, F, Y, lr, pos_weight, want_grads=False, stream=None):
     """One training step; returns (loss tensor [1], grads or None)."""
+    _check_x(F, net.dims[0], "F")
+    if not (isinstance(Y, torch.Tensor) and Y.dim() == 2 and tuple(Y.shape) == (F.shape[0], net.dims[3])):
+        raise ValueError("Y must have shape (batch, %d)" % net.dims[3])
     loss = torch.empty((1,), dtype=torch.float32, device=F.device)
     grads = torch.empty((net.param_count,), dtype=torch.float32, device=F.device) if want_grads else None
     _check(lib().kerdock_mlp_train_step(net.ptr, _dev(F, torch.float32, "F"), _dev(Y, torch.uint8, "Y"),
@@ -431,6 +467,7 @@ def kerdock_mlp_train_step(net, F, Y, lr, pos_weight, want_grads=False, stream=N
 
 
 def kerdock_features(h, X, stream=None):
+    _check_x(X, h.n)
     F = torch.empty((X.shape[0], h.info.d), dtype=torch.float32, device=X.device)
     _check(lib().kerdock_features(h.ptr, _dev(X, torch.float32, "X"), X.shape[0], _ptr(F), _stream(stream)))
     return F
@@ -441,18 +478,28 @@ def kerdock_learned_attach(h, net):
     h._net = net                      # keep the network alive with the handle
 
 
-def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, stream=None, chunk=0):
-    """Returns (idx, val, cnt, fallback)."""
+def kerdock_learned_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, stream=None, chunk=0,
+                          candidates=False):
+    """Returns (idx, val, cnt, fallback), and with candidates=True also the
+    candidate set C of every row ([B, s_max] int32, ascending, -1 padded)."""
+    _check_x(X, h.n)
     B = X.shape[0]
     dev = X.device
     if out is None:
         out = (torch.empty((B, s_max), dtype=torch.int32, device=dev),
                torch.empty((B, s_max), dtype=torch.float32, device=dev),
                torch.empty((B,), dtype=torch.int32, device=dev))
+    _check_out(out, B, s_max, dev)
     fb = torch.empty((B,), dtype=torch.int32, device=dev)
     p = ApplyParams(J=J, K=K, seed=seed, t0=t0, tau=tau, chunk=chunk)
+    cand = None
+    if candidates:
+        cand = torch.empty((B, s_max), dtype=torch.int32, device=dev)
+        p.dbg_survivors = cand.data_ptr()
     _check(lib().kerdock_learned_apply(h.ptr, _dev(X, torch.float32, "X"), B, float(eps), s_max, ctypes.byref(p),
                                        _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(fb), _stream(stream)))
+    if candidates:
+        return out[0], out[1], out[2], fb, cand
     return out[0], out[1], out[2], fb
 
 

@@ -114,3 +114,43 @@ def entry_tolerance(orc, ref, A64, k, d, dtype):
         lo, hi = np.minimum(lo, lo2), np.maximum(hi, hi2)
         used = orc.quant_e4m3(ref / s) * s
     return np.abs(hi - lo) * 1.0001 + 1e-30, used
+
+
+def check_outputs(orc, A64, X64, idx, val, cnt, r, info, eps, J, K, s_max, dtype, chunk=512):
+    """Outputs alone (entry points without debug dumps) against the oracle's
+    run on the same draws: every returned value is the exact a_i.x within
+    1e-5 relative, rows are ascending and keep |v| >= eps, padding is (-1, 0),
+    and the returned rows equal the oracle's output rows except rows at an
+    FP32 near-tie of the selection (oracle |mu| within the mu tolerance of
+    the s_max-th largest value) or with |a_i.x| within 1e-5 of eps.
+    Returns the number of such exceptions."""
+    k, d, n = info.k, info.d, A64.shape[1]
+    m = A64.shape[0]
+    exceptions = 0
+    for t in range(X64.shape[0]):
+        c = int(cnt[t])
+        assert 0 <= c <= s_max
+        gi, gv = idx[t][:c], val[t][:c].astype(np.float64)
+        assert np.all(np.diff(gi) > 0), "rows not ascending"
+        assert np.all(idx[t][c:] == -1) and np.all(val[t][c:] == 0)
+        v64 = A64[gi] @ X64[t]
+        scale = np.abs(A64[gi] * X64[t][None, :]).sum(1)
+        assert np.all(np.abs(gv - v64) <= 1e-5 * np.abs(v64) + 4 * U32 * U32 * n * scale + 1e-30)
+        assert np.all(np.abs(gv) >= eps)
+        oc = r["out_cnt"][t]
+        diff = np.setxor1d(r["out_idx"][t][:oc], gi)
+        if len(diff) == 0:
+            continue
+        ct = coef_tol(X64[t], n)
+        ent = orc.table_entries(A64, r["samples"][t], np.arange(m))
+        tolE, used = entry_tolerance(orc, ent, A64, k, d, dtype)
+        mt = mu_tolerance(used, r["coef"][t], J, K, tolE, np.full(J * K, ct), chunk)
+        a = np.abs(r["mu"][t])
+        order = np.lexsort((np.arange(m), -a))
+        theta = a[order[min(s_max, m) - 1]]
+        for i in diff:
+            near_eps = abs(abs(A64[i] @ X64[t]) - eps) <= 1e-5 * eps
+            near_cut = abs(a[i] - theta) <= mt[i] + mt.max() + 1e-12
+            assert near_eps or near_cut, "vector %d row %d returned by one side only" % (t, i)
+            exceptions += 1
+    return exceptions

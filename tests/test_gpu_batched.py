@@ -3,13 +3,14 @@ launch, graph capture and replay, autotuning.
 
 The persistent kernel runs the same device code as the single-handle path,
 with the same draws per workgroup, so its outputs must equal the per-handle
-kerdock_sparse_apply outputs bit for bit; those in turn are checked against
-the oracle by the parity tests (and once more here on one handle)."""
+kerdock_sparse_apply outputs bit for bit; every handle of a multi launch is
+also checked against the oracle directly (all three table types, and the
+n = 4096 BF16 matrix of the batched workload)."""
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import need_gpu
+from gpu_common import check_outputs, need_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -20,14 +21,16 @@ def unit_rows(B, n, seed):
     return torch.from_numpy((X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)).cuda()
 
 
-def setup(kd, dtype, shapes, seed=0):
-    hs, Xs = [], []
+def setup(kd, dtype, shapes, seed=0, keep_A=False):
+    hs, Xs, As = [], [], []
     for q, (m, n, B) in enumerate(shapes):
         rng = np.random.default_rng(seed + q)
         A = torch.from_numpy((rng.standard_normal((m, n)) / np.sqrt(n)).astype(np.float32)).cuda()
         hs.append(kd.kerdock_prepare(A, dtype))
         Xs.append(unit_rows(B, n, seed + 10 + q))
-    return hs, Xs
+        As.append(A.cpu().numpy().astype(np.float64) if keep_A else None)
+        del A
+    return (hs, Xs, As) if keep_A else (hs, Xs)
 
 
 SHAPES = [(64, 64, 3), (300, 100, 5), (1000, 1000, 4), (2048, 2048, 2), (700, 3000, 3)]
@@ -62,6 +65,48 @@ def test_multi_equals_single(orc, dtype):
     assert_same(ref, got)
     for h in hs:
         h.destroy()
+
+
+MODES = {"f32": "exact", "bf16": "bf16", "fp8": "fp8"}
+
+
+def multi_vs_oracle(orc, kd, dtype, shapes, params, s_max, seed):
+    hs, Xs, As = setup(kd, dtype, shapes, seed=seed, keep_A=True)
+    got = kd.kerdock_sparse_apply_multi(hs, Xs, params, EPS, s_max)
+    torch.cuda.synchronize()
+    infos = [h.info for h in hs]
+    outs = [tuple(o.cpu().numpy() for o in out) for out in got]
+    Xn = [X.cpu().numpy().astype(np.float64) for X in Xs]
+    for h in hs:
+        h.destroy()
+    del got, Xs
+    torch.cuda.empty_cache()
+    exc = 0
+    for q, (A64, X64, p, sm, info) in enumerate(zip(As, Xn, params, s_max, infos)):
+        r = orc.sparse_apply(A64, X64, p["J"], p["K"], EPS, sm, seed=p["seed"], t0=p["t0"],
+                             table_mode=MODES[dtype], debug=True)
+        idx, val, cnt = outs[q]
+        exc += check_outputs(orc, A64, X64, idx, val, cnt, r, info, EPS, p["J"], p["K"], sm, dtype)
+    return exc
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_multi_against_oracle(orc, dtype):
+    """Every handle of one persistent launch against the oracle's run of
+    Algorithm 1 on the same draws (outputs: exact values, rows equal up to
+    FP32 near-ties of the selection)."""
+    kd = need_gpu()
+    assert multi_vs_oracle(orc, kd, dtype, SHAPES, PARAMS, S_MAX, seed=50) <= 2
+
+
+def test_multi_n4096_bf16_against_oracle(orc):
+    """The batched workload's largest matrix (n = 4096, BF16 table of
+    68.8 GB) inside a multi-handle launch with a small one, against the
+    oracle."""
+    kd = need_gpu()
+    shapes = [(4096, 4096, 3), (256, 256, 5)]
+    params = [dict(J=64, K=2, seed=31, t0=3), dict(J=300, K=1, seed=32, t0=0)]
+    assert multi_vs_oracle(orc, kd, "bf16", shapes, params, [64, 40], seed=60) <= 1
 
 
 def test_multi_graph_replays(orc):

@@ -4,8 +4,9 @@ n = 2048 precision workload, batch 1024, J = 40960, K = 1, s_max = 320 (the
 equal-recall point the benchmark's calibration finds).  The oracle cannot
 afford all 1024 x 2048 estimates, so it checks sampled outputs one by one
 (draws of several vectors bit-exact, their coefficients, mu on the selected
-and on random rows); properties that hold at any size are checked on every
-vector (S is the exact top-s_max of the returned mu, survivor values equal
+and on random rows, and for one vector per table type the oracle's estimate
+on all m rows and its top-s_max against S); properties that hold at any size
+are checked on every vector (S is the exact top-s_max of the returned mu, survivor values equal
 A_S x, the threshold keeps exactly |v| >= eps)."""
 import numpy as np
 import pytest
@@ -76,10 +77,45 @@ def test_fullsize(orc, wl, dtype):
         rows = np.unique(np.concatenate([g["survivors"][t][:8], rng.integers(0, 2048, 8)]))
         ent = orc.table_entries(A64, ls, rows)                          # (N, R)
         tolE, used = entry_tolerance(orc, ent, A64[rows], info.k, info.d, dtype)
-        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), 768 if dtype == "fp8" else 512)
+        mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), GATHER_CHUNK[dtype])
         mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
         dmu = np.abs(g["mu"][t][rows] - mu_o)
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+        if t == 0:
+            check_survivors_all_rows(orc, A64, X64[t], ls, c64, ct, g["mu"][t], g["survivors"][t], info,
+                                     dtype, mode, GATHER_CHUNK[dtype], None, rng)
+
+
+# draws per partial sum of the per-vector form at J = 40960 (the library's
+# default for each table type)
+GATHER_CHUNK = {"f32": 512, "bf16": 512, "fp8": 768}
+
+
+def check_survivors_all_rows(orc, A64, x64, ls, c64, ct, mu_gpu, surv_gpu, info, dtype, mode, chunk, terms, rng):
+    """S of one vector against the oracle at the full configuration: the
+    oracle's median-of-means estimate on all m rows from the same draws, its
+    top-s_max (ties: smaller index), and the GPU's S equal except rows whose
+    oracle |mu| lies within the tolerance of the s_max-th value; the
+    tolerance is evaluated on the rows that differ, the rows around the cut
+    and random rows, where the GPU's mu must also lie within it."""
+    m = A64.shape[0]
+    mu_all = orc.mu_rows(A64, x64, ls, J, K, np.arange(m), mode)
+    a = np.abs(mu_all)
+    order = np.lexsort((np.arange(m), -a))
+    theta = a[order[S_MAX - 1]]
+    diff = set(order[:S_MAX].tolist()) ^ set(surv_gpu.tolist())
+    rows = np.unique(np.concatenate([np.array(sorted(diff), dtype=np.int64), order[S_MAX - 6:S_MAX + 6],
+                                     rng.integers(0, m, 8)])).astype(np.int64)
+    ent = orc.table_entries(A64, ls, rows)
+    tolE, used = entry_tolerance(orc, ent, A64[rows], info.k, info.d, dtype)
+    mt = mu_tolerance(used, c64, J, K, tolE, np.full(J * K, ct), chunk, terms)
+    dmu = np.abs(mu_gpu[rows] - mu_all[rows])
+    assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+    tol = dict(zip(rows.tolist(), mt.tolist()))
+    for i in diff:
+        assert abs(a[i] - theta) <= tol[i] + mt.max() + 1e-12, \
+            "row %d: oracle |mu| %.9g vs cut %.9g" % (i, a[i], theta)
+    assert len(diff) <= 2, "%d rows differ at near-ties" % len(diff)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
@@ -129,6 +165,9 @@ def test_fullsize_shared(orc, wl, dtype):
         mu_o = orc.mu_rows(A64, X64[t], ls, J, K, rows, mode)
         dmu = np.abs(g["mu"][t][rows] - mu_o)
         assert np.all(dmu <= mt), "mu excess %g" % (dmu - mt).max()
+        if t == 0:
+            check_survivors_all_rows(orc, A64, X64[t], ls, c64, ct, g["mu"][t], g["survivors"][t], info,
+                                     dtype, mode, J, shared_terms(J, dtype), rng)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])

@@ -134,6 +134,41 @@ def make_handle(kd, w, dtype="bf16"):
     return kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), dtype)
 
 
+def test_candidates_are_top_logits(orc):
+    """The candidate set C of the learned apply is the s_max rows of largest
+    logit, ties to the smaller index: compared with a numpy lexsort of the
+    network's logits (kerdock_mlp_forward on kerdock_features, the same
+    BF16 inputs), with negative logits and exact ties (output rows sharing
+    their weights and bias)."""
+    kd = need_gpu()
+    w = workloads.learned(48, n=256)
+    h = make_handle(kd, w)
+    m, d = h.m, h.info.d
+    dims = (d, 64, 64, m)
+    net = kd.kerdock_mlp_create(*dims, seed=5)
+    P = rand_params(dims, 6)
+    o3 = dims[1] * dims[0] + dims[1] + dims[2] * dims[1] + dims[2]     # W3 [m][d2], then b3 [m]
+    W3 = P[o3:o3 + m * dims[2]].reshape(m, dims[2])
+    b3 = P[o3 + m * dims[2]:]
+    for twin in (3, 40, 41, 200):
+        W3[twin] = W3[2]
+        b3[twin] = b3[2]
+    kd.kerdock_mlp_set_params(net, P)
+    kd.kerdock_learned_attach(h, net)
+    X = torch.from_numpy(w.X).cuda()
+    Z = kd.kerdock_mlp_forward(net, kd.kerdock_features(h, X)).cpu().numpy()
+    assert (Z < 0).any() and (Z > 0).any()
+    assert np.all(Z[:, 3] == Z[:, 2]) and np.all(Z[:, 200] == Z[:, 2])
+    for s_max in (1, 37, 128, m):
+        out = kd.kerdock_learned_apply(h, X, 0.05, s_max, 64, 1, 7, candidates=True)
+        cand = out[4].cpu().numpy()
+        for t in range(X.shape[0]):
+            order = np.lexsort((np.arange(m), -Z[t].astype(np.float64)))
+            assert np.array_equal(cand[t], np.sort(order[:s_max])), (s_max, t)
+    h.destroy()
+    net.destroy()
+
+
 def test_energy_check_without_proposal_gap(orc):
     """With C = every row the verified energy is the exact energy: no row may
     fall back (the energy path itself is consistent)."""

@@ -300,6 +300,36 @@ def test_errors(orc):
     h.destroy()
 
 
+def test_binding_rejects_bad_shapes(orc):
+    """The Python binding checks shapes before any launch: an X of the wrong
+    width or rank, or an output of the wrong shape or dtype, raises instead
+    of letting a kernel read or write past an allocation."""
+    kd = need_gpu()
+    h = prepare(kd, rand_A(40, 32, 1), "f32")
+    X = torch.from_numpy(unit_rows(3, 32, 1)).cuda()
+    bad_outs = [(torch.empty((3, 3), dtype=torch.int32, device="cuda"),
+                 torch.empty((3, 4), dtype=torch.float32, device="cuda"),
+                 torch.empty((3,), dtype=torch.int32, device="cuda")),
+                (torch.empty((3, 4), dtype=torch.int32, device="cuda"),
+                 torch.empty((3, 4), dtype=torch.float64, device="cuda"),
+                 torch.empty((3,), dtype=torch.int32, device="cuda")),
+                (torch.empty((3, 4), dtype=torch.int32, device="cuda"),
+                 torch.empty((3, 4), dtype=torch.float32, device="cuda"),
+                 torch.empty((2,), dtype=torch.int32, device="cuda"))]
+    for fn in (kd.kerdock_sparse_apply, kd.kerdock_sparse_apply_shared):
+        for Xb in (X[:, :31].contiguous(), torch.zeros((3, 33), device="cuda"), X.view(-1)):
+            with pytest.raises(ValueError):
+                fn(h, Xb, 0.1, 4, 8, 2, 0)
+        for out in bad_outs:
+            with pytest.raises((ValueError, TypeError)):
+                fn(h, X, 0.1, 4, 8, 2, 0, out=out)
+    with pytest.raises(ValueError):
+        kd.kerdock_features(h, torch.zeros((2, 16), device="cuda"))
+    with pytest.raises(ValueError):
+        kd.kerdock_sparse_apply_multi([h], [torch.zeros((2, 16), device="cuda")], [dict(J=4, K=1)], 0.1, [4])
+    h.destroy()
+
+
 @pytest.mark.parametrize("shared", [False, True])
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_non_finite_input_is_flagged(orc, shared, dtype):
