@@ -147,6 +147,26 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
                          int32_t *out_cnt, void *stream);
 
 /*
+ * kerdock_sparse_apply_static -- kerdock_sparse_apply for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels, draws and
+ * results as kerdock_sparse_apply (bit for bit), but the workspace (chunk
+ * partial sums, S, survivor values, row grouping) lives in a fixed device
+ * array of KERDOCK_STATIC_SCRATCH_BYTES inside the library, one per device,
+ * held until the process ends; the call allocates nothing.  A call whose
+ * workspace would exceed it fails with INVALID_ARG (use fewer vectors per
+ * call; the workspace grows with batch K ceil(J / chunk) 4 pitch bytes).
+ * kernel_ms must be NULL.  Every call on a device shares that device's
+ * array, so calls that overlap in time on one device (different streams,
+ * host threads) race and must be serialised by the caller.
+ * Errors: those of kerdock_sparse_apply, with OOM replaced by INVALID_ARG.
+ */
+#define KERDOCK_STATIC_SCRATCH_BYTES (64u << 20)
+int kerdock_sparse_apply_static(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                                const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                                int32_t *out_cnt, void *stream);
+
+/*
  * kerdock_reserve -- allocate the workspace that kerdock_sparse_apply needs
  * for up to `batch` vectors with N = J K draws and the given s_max, so that
  * later calls within these sizes allocate nothing (needed before capturing

@@ -8,6 +8,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -180,9 +181,13 @@ static int check_apply_args(kerdock_handle h, const float *X, int batch, float e
     return KERDOCK_OK;
 }
 
-int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
-                   const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
-                   const int32_t *active, void *stream) {
+// The streaming step with the workspace either the handle's own (ext_ws
+// NULL: grown with hipMalloc when too small) or a caller-provided device
+// buffer of ext_bytes (then nothing is allocated: sizes that do not fit are
+// rejected, kernel_ms is not supported).
+static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                    const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
+                    const int32_t *active, void *stream, void *ext_ws, size_t ext_bytes) {
     {
         const int c = check_apply_args(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt);
         if (c != KERDOCK_OK) return c == 1 ? KERDOCK_OK : c;
@@ -193,9 +198,20 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     const int cpb = (J + chunk - 1) / chunk;
 
     const Workspace lay = workspace_layout(h, batch, J, K, s_max, chunk);
-    int rc = ensure_workspace(h, lay.total);
-    if (rc != KERDOCK_OK) return rc;
-    char *ws = reinterpret_cast<char *>(h->ws);
+    char *ws;
+    int rc = KERDOCK_OK;
+    if (ext_ws) {
+        if (lay.total > ext_bytes)
+            return fail(KERDOCK_ERR_INVALID_ARG, "this call needs " + std::to_string(lay.total) +
+                                                     " bytes of workspace, more than the " + std::to_string(ext_bytes) +
+                                                     " bytes of the static scratch (use fewer vectors per call)");
+        if (p->kernel_ms) return fail(KERDOCK_ERR_INVALID_ARG, "kernel_ms is not supported without allocation");
+        ws = reinterpret_cast<char *>(ext_ws);
+    } else {
+        rc = ensure_workspace(h, lay.total);
+        if (rc != KERDOCK_OK) return rc;
+        ws = reinterpret_cast<char *>(h->ws);
+    }
     float *partial = reinterpret_cast<float *>(ws + lay.partial);
     int32_t *surv = reinterpret_cast<int32_t *>(ws + lay.surv);
     int32_t *nsurv = reinterpret_cast<int32_t *>(ws + lay.nsurv);
@@ -250,6 +266,41 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
     }
     if (p->dbg_survivors)
         KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
+    return KERDOCK_OK;
+}
+
+int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                   const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
+                   const int32_t *active, void *stream) {
+    return apply_ws(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, active, stream, nullptr, 0);
+}
+
+// ---------------------------------------------------- static scratch ----
+// Device scratch of fixed size for kerdock_sparse_apply_static (callers that
+// cannot allocate).  In host code `scratch` names a host-side stand-in, not
+// a device address: its address on each device is looked up once, with that
+// device current, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[KERDOCK_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+static int static_scratch(int device, void **out) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(KERDOCK_ERR_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
     return KERDOCK_OK;
 }
 
@@ -442,6 +493,17 @@ int kerdock_sparse_apply(kerdock_handle h, const float *X, int batch, float eps,
                          const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
                          int32_t *out_cnt, void *stream) {
     return kd::apply_internal(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, nullptr, stream);
+}
+
+int kerdock_sparse_apply_static(kerdock_handle h, const float *X, int batch, float eps, int s_max,
+                                const kerdock_apply_params *p, int32_t *out_idx, float *out_val,
+                                int32_t *out_cnt, void *stream) {
+    if (!h) return fail(KERDOCK_ERR_NOT_PREPARED, "NULL handle");
+    void *ws = nullptr;
+    const int rc = static_scratch(h->device, &ws);
+    if (rc != KERDOCK_OK) return rc;
+    return kd::apply_ws(h, X, batch, eps, s_max, p, out_idx, out_val, out_cnt, nullptr, stream, ws,
+                        KERDOCK_STATIC_SCRATCH_BYTES);
 }
 
 int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, float eps, int s_max,

@@ -53,6 +53,10 @@ EXPORTS = {
                                             ctypes.c_float, ctypes.c_int,
                                             ctypes.POINTER(ApplyParams), ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kerdock_sparse_apply_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                   ctypes.c_float, ctypes.c_int,
+                                                   ctypes.POINTER(ApplyParams), ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kerdock_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int]),
     "kerdock_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
@@ -265,6 +269,16 @@ def kerdock_sparse_apply(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, 
     of the four kernels, timed with HIP events on the call's stream."""
     return _sparse_apply("kerdock_sparse_apply", h, X, eps, s_max, J, K, seed, t0, tau, out, debug, stream,
                          kernel_ms, chunk)
+
+
+def kerdock_sparse_apply_static(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
+                                stream=None, chunk=0):
+    """As kerdock_sparse_apply, with the workspace in the library's fixed
+    device scratch (KERDOCK_STATIC_SCRATCH_BYTES per device): the call
+    allocates nothing in the library (pass `out` to avoid torch allocating
+    the outputs too); calls that overlap on one device race."""
+    return _sparse_apply("kerdock_sparse_apply_static", h, X, eps, s_max, J, K, seed, t0, tau, out, debug, stream,
+                         None, chunk)
 
 
 def kerdock_sparse_apply_shared(h, X, eps, s_max, J, K, seed, t0=0, tau=0.0, out=None, debug=False,
