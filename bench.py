@@ -32,6 +32,7 @@ METRIC = "thresholded-Ax/sec at n=2048, eps=0.05: plain vs BF16/batched/learned;
 N_GRID = [8192, 12288, 16384, 20480, 24576, 28672, 32768, 40960, 49152, 65536, 98304, 131072]
 BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
 PLANTED_GRID = [512, 1024, 2048, 4096, 8192, 16384, 32768, 65536]
+MU_F32 = {}          # mu-hat of the FP32 table (first vectors), the reference of the other table types
 
 
 def log(*a):
@@ -119,6 +120,22 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
     col_bytes = info.m * BYTES[dt]
     gather_bytes = B * N * col_bytes
     gbps = gather_bytes / (kern[1] * 1e-3) / 1e9
+    # the error the table type itself adds: mu-hat of the first 8 vectors
+    # against the FP32 table's mu-hat from the same draws
+    dbg = kd.kerdock_sparse_apply(h, X[:8].contiguous(), args.eps, args.s_max, J, K, args.seed, t0=0, debug=True,
+                                  chunk=args.chunk)
+    mu = dbg[3]["mu"].double().cpu().numpy()
+    surv = dbg[3]["survivors"].cpu().numpy()
+    mu_err = None
+    if dt == "f32":
+        MU_F32.update(mu=mu, surv=surv, J=J, K=K)
+    elif MU_F32.get("J") == J and MU_F32.get("K") == K:
+        ref = MU_F32["mu"]
+        mu_err = {"max_abs_vs_f32_table": float(np.abs(mu - ref).max()),
+                  "max_rel_to_max_mu": float(np.max(np.abs(mu - ref).max(1) / np.abs(ref).max(1))),
+                  "survivor_sets_equal_fraction": float(np.mean([np.array_equal(a, b) for a, b in
+                                                                 zip(surv, MU_F32["surv"])])),
+                  "vectors": 8}
     shared = None
     if args.shared:
         # the same (J, K) with draws shared by groups of 64 x (matrix-product form)
@@ -148,9 +165,10 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
         "x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3, "J": J, "K": K, "N": N,
         "calib_recall": rc, "recall_mean": float(np.mean(rec)), "recall_min": float(np.min(rec)),
         "max_abs_err_vs_fp64": err, "prepare_s": prep, "table_GB": info.table_bytes / 1e9,
-        "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
+        "kernel_ms": {"draws_sort": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
         "gather_GBps": gbps, "gather_frac_hbm": gbps / HBM_PEAK_GBPS,
         "gather_bytes_per_launch": gather_bytes, "shared_draws": shared, "autotuned": tuned,
+        "mu_error_vs_f32_table": mu_err,
         "chunk": min(J, args.chunk or (tuned["chunk"] if tuned else
                                        min(768 if dt == "fp8" else 512, max(16, -(-J // 8))))),
     }
@@ -168,9 +186,10 @@ def planted_recall(surv, supports):
     return r
 
 
-def calibrate_planted(kd, h, Xc, sup_c, eps, s_max, target, seed):
+def calibrate_planted(kd, h, Xc, sup_c, eps, s_max, target, seed, curve=None):
     """Cheapest (J, K) whose selected rows S hold >= target of the planted
-    support on average (the eps-support of these workloads is mostly empty)."""
+    support on average (the eps-support of these workloads is mostly empty);
+    curve, when given, receives (N, best planted recall) for every N tried."""
     best = None
     for N in PLANTED_GRID:
         best = None
@@ -181,9 +200,142 @@ def calibrate_planted(kd, h, Xc, sup_c, eps, s_max, target, seed):
             r = sum(r) / len(r)
             if best is None or r > best[2]:
                 best = (J, K, r)
+        if curve is not None:
+            curve.append((N, best[2]))
         if best[2] >= target:
             return best
     return best
+
+
+def bucket_form(kd, torch, np, workloads, args):
+    """Grouping the draws by basis where the direct coefficient sums are not
+    hidden behind the column stream: the precision workload's x (n = 2048,
+    d = 4096, 2049 bases) against the first 256 rows of its A (FP8 table,
+    256-byte columns), J = 40960 (20 draws per basis), K = 1, 1024 x; the same
+    call with the draws in drawing order and grouped by basis."""
+    w = workloads.precision(batch=args.batch)
+    A = torch.from_numpy(np.ascontiguousarray(w.A[:256])).cuda()
+    X = torch.from_numpy(w.X).cuda()
+    B, J, K, s_max = X.shape[0], 40960, 1, 64
+    h = kd.kerdock_prepare(A, "fp8")
+    out = (torch.empty((B, s_max), dtype=torch.int32, device="cuda"),
+           torch.empty((B, s_max), dtype=torch.float32, device="cuda"),
+           torch.empty((B,), dtype=torch.int32, device="cuda"))
+    res = {"workload": "n=2048 x (precision workload), first 256 rows of its A, FP8 table, J=%d K=%d, %d x, "
+                       "s_max=%d" % (J, K, B, s_max)}
+    ms = (ctypes.c_float * 4)()
+    saved = os.environ.get("KERDOCK_BUCKET")
+    for mode in ("0", "1"):
+        os.environ["KERDOCK_BUCKET"] = mode
+        kd.kerdock_reserve(h, B, J, K, s_max)
+        kd.kerdock_sparse_apply(h, X, args.eps, s_max, J, K, args.seed, out=out)
+        torch.cuda.synchronize()
+        kern = np.zeros(4)
+        t0 = time.perf_counter()
+        for sidx in range(args.steps):
+            kd.kerdock_sparse_apply(h, X, args.eps, s_max, J, K, args.seed, t0=sidx * B, out=out, kernel_ms=ms)
+            kern += np.array(ms[:4])
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        kern /= args.steps
+        res["grouped" if mode == "1" else "drawing_order"] = {
+            "x_per_s": B / el, "ms_per_step": el * 1e3,
+            "kernel_ms": {"draws_sort": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
+            "gather_GBps": B * J * K * 256 / (kern[1] * 1e-3) / 1e9}
+    if saved is None:
+        del os.environ["KERDOCK_BUCKET"]
+    else:
+        os.environ["KERDOCK_BUCKET"] = saved
+    res["speedup_from_grouping"] = res["grouped"]["x_per_s"] / res["drawing_order"]["x_per_s"]
+    log("grouping by basis (m = 256 FP8, n = 2048): drawing order %.0f x/s (gather %.2f ms), grouped %.0f x/s "
+        "(sort %.2f + gather %.2f ms)" % (res["drawing_order"]["x_per_s"], res["drawing_order"]["kernel_ms"]["gather"],
+                                          res["grouped"]["x_per_s"], res["grouped"]["kernel_ms"]["draws_sort"],
+                                          res["grouped"]["kernel_ms"]["gather"]))
+    h.destroy()
+    torch.cuda.empty_cache()
+    return res
+
+
+def planted_ceiling(A64, X64, supports, s_max, np):
+    """Planted-support recall of the s_max rows of largest exact |Ax|: what an
+    estimator without error would reach (planted entries below the noise of
+    y are not recoverable by any ranking)."""
+    Y = X64 @ A64.T
+    r = []
+    for t, sup in enumerate(supports):
+        top = np.argsort(-np.abs(Y[t]), kind="stable")[:s_max]
+        r.append(len(set(top.tolist()) & set(sup.tolist())) / len(sup))
+    return float(np.mean(r))
+
+
+def planted_curve(kd, h, Xc, sup_c, eps, s_max, seed, grid):
+    """Planted-support recall of S against N = J (K = 1) on a calibration batch."""
+    curve = []
+    for N in grid:
+        out = kd.kerdock_sparse_apply(h, Xc, eps, s_max, N, 1, seed, t0=1 << 40, debug=True)
+        r = planted_recall(out[3]["survivors"].cpu().numpy(), sup_c)
+        curve.append((N, sum(r) / len(r)))
+    return curve
+
+
+def plain_form(kd, torch, np, workloads, args):
+    """The plain method on a general matrix: n = 1024, A with i.i.d.
+    N(0, 1/n) entries, 256 unit x = A^-1 y normalised with y 16-sparse N(0,1)
+    plus N(0, 1e-4), eps = 0.05, s_max = 10 s = 160, FP32 table (and BF16 for
+    comparison).  The eps-support of Ax is empty for nearly every x, so the
+    equal-recall point is taken on the planted support of y inside S: the
+    cheapest N = J (K = 1) of the grid whose planted recall reaches 0.99 of
+    what the exact ranking of |Ax| reaches, else the largest N; the
+    recall-vs-N curve is reported."""
+    w = workloads.plain()
+    wc = workloads.plain(batch=128, seed_X=workloads.SEED_X + 88)
+    s_max = 10 * w.s
+    A64, X64 = w.A.astype(np.float64), w.X.astype(np.float64)
+    sup, Ax = eps_supports(A64, X64, args.eps)
+    ceiling = planted_ceiling(A64, wc.X.astype(np.float64), wc.supports, s_max, np)
+    target = args.recall * ceiling
+    A = torch.from_numpy(w.A).cuda()
+    X = torch.from_numpy(w.X).cuda()
+    Xc = torch.from_numpy(wc.X).cuda()
+    grid = PLANTED_GRID + [131072, 262144]
+    res = {"workload": "n=1024 A iid N(0,1/n), %d x = A^-1 y normalised, y 16-sparse N(0,1) + N(0,1e-4), "
+                       "eps=%g, s_max=%d; equal recall on the planted support of y (target %.3f = %g of the "
+                       "exact-ranking ceiling %.4f)" % (w.batch, args.eps, s_max, target, args.recall, ceiling),
+           "eps_support_empty_fraction": float(np.mean([len(q) == 0 for q in sup])),
+           "max_abs_Ax": float(np.abs(Ax).max()), "planted_ceiling": ceiling, "planted_target": target}
+    B = w.batch
+    for dt in ("f32", "bf16"):
+        h = kd.kerdock_prepare(A, dt)
+        curve = planted_curve(kd, h, Xc, wc.supports, args.eps, s_max, args.seed, grid)
+        N = next((n_ for n_, r in curve if r >= target), grid[-1])
+        kd.kerdock_reserve(h, B, N, 1, s_max)
+        out = (torch.empty((B, s_max), dtype=torch.int32, device="cuda"),
+               torch.empty((B, s_max), dtype=torch.float32, device="cuda"),
+               torch.empty((B,), dtype=torch.int32, device="cuda"))
+        for sidx in range(args.warmup):
+            kd.kerdock_sparse_apply(h, X, args.eps, s_max, N, 1, args.seed, t0=sidx * B, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sidx in range(args.steps):
+            kd.kerdock_sparse_apply(h, X, args.eps, s_max, N, 1, args.seed, t0=sidx * B, out=out)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dbg = kd.kerdock_sparse_apply(h, X, args.eps, s_max, N, 1, args.seed, t0=0, debug=True)
+        rp = planted_recall(dbg[3]["survivors"].cpu().numpy(), w.supports)
+        idx, cnt = dbg[0].cpu().numpy(), dbg[2].cpu().numpy()
+        rec = recall_of(idx, cnt, sup)
+        res[dt] = {"x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3, "J": N, "K": 1,
+                   "target_reached": bool(dict(curve)[N] >= target),
+                   "planted_recall_mean": float(np.mean(rp)), "planted_recall_min": float(np.min(rp)),
+                   "eps_recall_mean_nonempty": float(np.mean(rec)) if rec else None,
+                   "curve_planted_recall_vs_N": curve, "table_GB": h.info.table_bytes / 1e9}
+        log("plain %s: N=%d %.0f x/s planted recall %.4f (ceiling %.4f)" % (dt, N, res[dt]["x_per_s"],
+                                                                           res[dt]["planted_recall_mean"], ceiling))
+        h.destroy()
+        torch.cuda.empty_cache()
+    res["bf16_speedup_vs_f32"] = res["bf16"]["x_per_s"] / res["f32"]["x_per_s"]
+    res["dense"] = dense_baselines(torch, A, X)
+    return res
 
 
 def small_handles_form(kd, torch, np, workloads, args):
@@ -252,20 +404,30 @@ def batched_form(kd, torch, np, workloads, args):
         sup, Ax = eps_supports(A64, X64, args.eps)
         exact.append((sup, Ax))
     res = {"workload": "n=(256,1024,4096) Gaussian A, (512,1024,2560) x, s~U{4..64}, eps=%g, "
-                       "s_max=min(640,n); calibrated on planted-support recall of S >= %g, or the "
-                       "largest N of the grid (%d) when that is not reached; equal N gives equal "
-                       "recall across the forms" % (args.eps, args.recall, PLANTED_GRID[-1]),
+                       "s_max=min(640,n); calibrated on planted-support recall of S >= %g of what the "
+                       "exact ranking of |Ax| reaches, or the largest N of the grid (%d) when that is not "
+                       "reached; equal N gives equal recall across the forms" % (args.eps, args.recall,
+                                                                                   PLANTED_GRID[-1]),
            "eps_support_empty_fraction": float(np.mean([len(s) == 0 for e in exact for s in e[0]]))}
+
+    # what the exact ranking of |Ax| reaches on the planted support (planted
+    # entries below the noise of y are lost to any estimator); the target is
+    # args.recall of it
+    ceil = [planted_ceiling(w.A.astype(np.float64), c.X.astype(np.float64), c.supports, sm, np)
+            for w, c, sm in zip(wl, wc, smax)]
+    res["planted_ceiling"] = ceil
 
     def run_form(dt, batched, shared=False):
         hs = [kd.kerdock_prepare(A, dt) for A in As]
         params = []
         for q, h in enumerate(hs):
-            J, K, r = calibrate_planted(kd, h, Xcs[q], wc[q].supports, args.eps, smax[q], args.recall,
-                                        args.seed + q)
+            curve = []
+            target = args.recall * ceil[q]
+            J, K, r = calibrate_planted(kd, h, Xcs[q], wc[q].supports, args.eps, smax[q], target,
+                                        args.seed + q, curve)
             params.append(dict(J=J, K=K, seed=args.seed + q, t0=0, calib_planted_recall=r,
-                               target_reached=bool(r >= args.recall)))
-            log("  batched %s n=%d: J=%d K=%d planted recall %.4f" % (dt, wl[q].n, J, K, r))
+                               target=target, target_reached=bool(r >= target), curve=curve))
+            log("  batched %s n=%d: J=%d K=%d planted recall %.4f (target %.4f)" % (dt, wl[q].n, J, K, r, target))
         for q, h in enumerate(hs):
             kd.kerdock_reserve(h, wl[q].batch, params[q]["J"], params[q]["K"], smax[q])
         outs = [(torch.empty((w.batch, sm), dtype=torch.int32, device="cuda"),
@@ -305,7 +467,8 @@ def batched_form(kd, torch, np, workloads, args):
             rec_eps += recall_of(idx, cnt, exact[q][0])
         form = {"x_per_s": total * args.steps / el, "ms_per_step": el / args.steps * 1e3,
                 "params": [dict(n=w.n, J=p["J"], K=p["K"], calib_planted_recall=p["calib_planted_recall"],
-                                target_reached=p["target_reached"]) for w, p in zip(wl, params)],
+                                target=p["target"], target_reached=p["target_reached"],
+                                curve_planted_recall_vs_N=p["curve"]) for w, p in zip(wl, params)],
                 "eps_recall_mean_nonempty": float(np.mean(rec_eps)) if rec_eps else None,
                 "table_GB": sum(h.info.table_bytes for h in hs) / 1e9}
         if plan is not None:
@@ -392,7 +555,7 @@ def paper_form(kd, torch, np, workloads, args):
         res[dt] = {"x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3, "chunk": ch,
                    "x_per_s_one_per_call": single, "exact_recovery": exact / B, "prepare_s": prep,
                    "table_GB": h.info.table_bytes / 1e9,
-                   "kernel_ms": {"draws_coef": kern[0], "gather": kern[1], "select": kern[2],
+                   "kernel_ms": {"draws_sort": kern[0], "gather": kern[1], "select": kern[2],
                                  "survivors": kern[3]},
                    "gather_GBps": gbps}
         log("paper regime %s: prepare %.1f s, %.0f x/s batched (gather %.3f ms %.0f GB/s, select "
@@ -441,7 +604,7 @@ def paper_form(kd, torch, np, workloads, args):
     return res
 
 
-def toy_sweep(kd, torch, np, workloads, args):
+def toy_sweep(kd, torch, np, workloads, args, pns=None):
     """Section 2.1's toy model at n = 4096: A orthogonal, every entry of Ax
     N(0,1) with probability p, x normalised, s = 10 p n rows kept, eps =
     alpha / sqrt(p n).  For p n from 2 to 400 (the model's range is 1 << p n
@@ -458,7 +621,7 @@ def toy_sweep(kd, torch, np, workloads, args):
     base = dense_baselines(torch, A, Xd)
     del Xd
     rows = []
-    for pn in args.sweep_pn:
+    for pn in (pns or args.sweep_pn):
         p = pn / n
         eps = alpha / np.sqrt(pn)
         s_max = int(min(n, np.ceil(10 * pn)))
@@ -691,6 +854,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-form workload")
     ap.add_argument("--no-paper", action="store_true", help="skip the numerical-section regime")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-method workload (n = 1024 Gaussian A)")
+    ap.add_argument("--no-bucket", action="store_true",
+                    help="skip the comparison of draws in drawing order and grouped by basis (m = 256 FP8)")
+    ap.add_argument("--no-toy", action="store_true",
+                    help="skip the three-point toy-model sweep (p n = 2, 5, 20) of the default run")
     ap.add_argument("--chunk", type=int, default=0,
                     help="draws per FP32 partial sum in the precision forms (0: the library's default)")
     ap.add_argument("--autotune", action="store_true",
@@ -755,14 +923,20 @@ def main():
     head_dt = "f32" if "f32" in forms else next(iter(forms))
     for dt, r in forms.items():
         r["speedup_vs_plain"] = r["x_per_s"] / head["x_per_s"]
+    del A, X, Xc
+    torch.cuda.empty_cache()
+    if not args.no_plain:
+        forms["plain"] = plain_form(kd, torch, np, workloads, args)
+    if not args.no_bucket:
+        forms["grouping_by_basis"] = bucket_form(kd, torch, np, workloads, args)
     if not args.no_batched:
-        del A, X, Xc
-        torch.cuda.empty_cache()
         forms["batched"] = batched_form(kd, torch, np, workloads, args)
     if not args.no_learned:
         forms["learned"] = learned_form(kd, torch, np, workloads, args)
     if not args.no_paper:
         forms["paper_regime"] = paper_form(kd, torch, np, workloads, args)
+    if not args.no_toy:
+        forms["toy_sweep"] = toy_sweep(kd, torch, np, workloads, args, pns=[2, 5, 20])
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A64, X64, head["J"], head["K"], args.eps, args.s_max, args.seed)

@@ -85,13 +85,17 @@ typedef struct {
     float *dbg_values;     /* [batch][s_max] a_i.x for every i in S, 0 padded */
     /* optional host [4]: when set, the call records HIP events on `stream`
        around its kernels, waits for them and stores their durations in ms:
-       [0] 0 (draws and coefficients run inside the gather kernel),
-       [1] draws + coefficients + gather, [2] batch means, median and
-       selection, [3] survivor dots and threshold. */
+       [0] grouping of the draws by basis (0 when the call does not group
+       them), [1] draws, coefficients and gather, [2] batch means, median
+       and selection, [3] survivor dots and threshold. */
     float *kernel_ms;
-    /* draws per FP32 partial sum of a batch mean.  The exact rounding of mu
-       depends on this and on nothing else about the launch (batch size,
-       workgroup shape and unroll leave it unchanged): 0 = the value that
+    /* draws per FP32 partial sum of a batch mean: consecutive draws of
+       the batch, in drawing order or, when the call groups its draws by
+       basis (a cost rule of the handle: a few draws per basis on average
+       and columns short against x, or the autotuned choice), in that
+       order.  The exact rounding of mu depends on this and on nothing else
+       about the launch (batch size, workgroup shape and unroll leave it
+       unchanged): 0 = the value that
        kerdock_autotune stored in the handle, else min(C, max(16,
        ceil(J / 8))) with C = 768 for FP8 tables and 512 otherwise;
        1..1024 = that many (capped at J); other values are INVALID_ARG. */
@@ -176,9 +180,11 @@ int kerdock_reserve(kerdock_handle h, int batch, int J, int K, int s_max);
 
 /*
  * kerdock_autotune -- pick the gather shape for this handle: draws per
- * workgroup (256, 512, 1024) and draws in flight per thread, by timing the
- * draws + gather kernel on X (device, batch x n) with N = J K draws, three
- * runs each (the first one discarded).  The choice is kept in the handle for
+ * workgroup (256, 512, 1024), draws in flight per thread and (when a batch
+ * holds at least two draws per basis on average) whether the draws are
+ * grouped by basis first, by timing the draws + gather kernels on X
+ * (device, batch x n) with N = J K draws, three runs each (the first one
+ * discarded).  The choice is kept in the handle for
  * later calls and, when the environment variable KERDOCK_TUNE_CACHE names a
  * file, appended to it and read back by later kerdock_prepare calls of the
  * same shape.  Outputs (host, optional): best_chunk, best_unroll, best_ms.
@@ -301,17 +307,22 @@ int kerdock_learned_attach(kerdock_handle h, kerdock_mlp net);
 /*
  * kerdock_learned_apply -- h_eps(Ax) with the learned proposal: features,
  * logits, C = the s_max rows of largest logit, exact a_i.x on C (compensated
- * dot product), threshold at eps; then the exact energy |Ax|^2 = x^T G x is
- * compared with the verified energy sum_{i in C} (a_i.x)^2 and every row
- * whose verified energy falls short by more than eps^2 / 2 is recomputed by
- * the plain streaming step of kerdock_sparse_apply with parameters p (a row
- * of h_eps(Ax) outside C removes at least eps^2 from the verified energy, so
- * no such row is accepted without the fallback).  fallback (device [B]
- * int32) receives 1 for the recomputed rows.  Outputs as in
- * kerdock_sparse_apply.  Debug: when p->dbg_survivors is given it receives
- * the candidate set C of every row ([B][s_max], ascending, padded with -1);
- * the other debug fields and kernel_ms are ignored.  Errors: NOT_PREPARED
- * (no attached network), INVALID_ARG, OOM, HIP.
+ * dot product), threshold at eps; then the energy |Ax|^2 = x^T G x (G = A^T A
+ * as a compensated pair, quadratic form with compensated sums) is compared
+ * with the verified energy S = sum_{i in C} (a_i.x)^2, together with a
+ * rigorous bound B on the FP32 rounding of both; a row is kept only when
+ * |Ax|^2 - S <= eps^2 / 2 and B < eps^2 / 2, every other row is recomputed by
+ * the plain streaming step of kerdock_sparse_apply with parameters p.  A row
+ * of h_eps(Ax) outside C leaves at least eps^2 of energy outside C, so no
+ * such row is ever accepted without the fallback, in floating point too.
+ * (B grows like (m u)^2 |A|_F^2 |x|^2: when it reaches eps^2 / 2 every row
+ * falls back.)  fallback (device [B] int32) receives 1 for the recomputed
+ * rows.  Outputs as in kerdock_sparse_apply.  Debug: when p->dbg_survivors
+ * is given it receives the candidate set C of every row ([B][s_max],
+ * ascending, padded with -1); when p->dbg_mu is given (m >= 3), entries 0,
+ * 1, 2 of its row t receive the computed |Ax|^2, S and B of vector t; the
+ * other debug fields and kernel_ms are ignored.  Errors: NOT_PREPARED (no
+ * attached network), INVALID_ARG, OOM, HIP.
  */
 int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, int s_max,
                           const kerdock_apply_params *p, int32_t *out_idx, float *out_val,

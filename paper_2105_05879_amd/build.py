@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkerdock.so")
-SOURCES = ["kerdock_set.cpp", "build_kernels.hip", "apply_kernels.hip", "multi.hip", "shared.hip", "mlp.hip",
+SOURCES = ["kerdock_set.cpp", "build_kernels.hip", "apply_kernels.hip", "multi.hip", "shared.hip", "mlp.hip", "energy.hip",
            "learned.cpp", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -28,6 +28,7 @@ int launch_read_columns(kerdock_dtype dt, const void *table, int m, int pitch, i
                         const float *scales, const uint32_t *ells, int count, float *out,
                         hipStream_t s);
 int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int unroll, hipStream_t s);
+int launch_draw_sort(const DGArgs &a, int batch, int K, hipStream_t s);
 int gather_chunk_max();
 int launch_select(const SelArgs &a, int batch, hipStream_t s);
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
@@ -80,18 +81,40 @@ static int gather_unroll(const kerdock_handle_s *h) {
     return env_int("KERDOCK_UNROLL", h->tune_unroll > 0 ? h->tune_unroll : 8);
 }
 
-// workspace layout of the streaming step
+// Whether a call groups its draws by basis before the gather (draw_sort and
+// the per-basis transform of the coefficients).  It pays only where the
+// direct coefficient sums are not hidden behind the column stream: runs of
+// at least four draws per basis on average (J >= 4 (d/2 + 1)) and columns
+// short against the length of x (m b_T <= 1024 P bytes, P = 1 for n <= 2048,
+// else 2).  kerdock_autotune may settle it by timing; KERDOCK_BUCKET=0 / 1
+// overrides both.  The summation order of the batch means follows it.
+int use_bucket(const kerdock_handle_s *h, int J) {
+    const int forced = env_int("KERDOCK_BUCKET", -1);
+    if (forced == 0 || forced == 1) return forced;
+    if (h->tune_bucket >= 0) return h->tune_bucket;
+    const int64_t bases = h->d / 2 + 1;
+    const int64_t col = (int64_t)h->pitch * (int64_t)dtype_bytes(h->dtype);
+    const int P = h->n <= 2048 ? 1 : 2;
+    return ((int64_t)J >= 4 * bases && col <= 1024 * P) ? 1 : 0;
+}
+
+// workspace layout of the streaming step (perm only for debug dumps)
 struct Workspace {
-    size_t partial, surv, nsurv, svals, rows, total;
+    size_t partial, jlist, sorted, perm, surv, nsurv, svals, rows, total;
 };
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max, int chunk) {
+static Workspace workspace_layout(const kerdock_handle_s *h, int batch, int J, int K, int s_max, int chunk,
+                                  bool debug = false) {
     const size_t cpb = (J + chunk - 1) / chunk;
+    const size_t draws = use_bucket(h, J) ? (size_t)batch * J * K * 4 : 0;
     Workspace w;
     size_t off = 0;
     w.partial = off; off += align256((size_t)batch * K * cpb * h->pitch * 4);
+    w.jlist = off;   off += align256(draws);
+    w.sorted = off;  off += align256(draws);
+    w.perm = off;    off += debug ? align256(draws) : 0;
     w.surv = off;    off += align256((size_t)batch * s_max * 4);
     w.nsurv = off;   off += align256((size_t)batch * 4);
     w.svals = off;   off += align256((size_t)batch * s_max * 4);
@@ -131,18 +154,19 @@ static void free_handle(kerdock_handle_s *h) {
     delete h;
 }
 
-// Tuning cache: one line "m n dtype K chunk unroll" per tuned shape, in the
+// Tuning cache: one line "m n dtype K chunk unroll bucket" per tuned shape, in the
 // file named by KERDOCK_TUNE_CACHE (read at prepare, appended by autotune).
 static void cache_lookup(kerdock_handle_s *h) {
     const char *path = getenv("KERDOCK_TUNE_CACHE");
     if (!path || !*path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    int m, n, dt, K, c, u;
-    while (fscanf(f, "%d %d %d %d %d %d", &m, &n, &dt, &K, &c, &u) == 6)
+    int m, n, dt, K, c, u, bk;
+    while (fscanf(f, "%d %d %d %d %d %d %d", &m, &n, &dt, &K, &c, &u, &bk) == 7)
         if (m == h->m && n == h->n && dt == (int)h->dtype) {
             h->tune_chunk = c;
             h->tune_unroll = u;
+            h->tune_bucket = bk;
         }
     fclose(f);
 }
@@ -152,7 +176,7 @@ static void cache_store(const kerdock_handle_s *h, int K) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%d %d %d %d %d %d\n", h->m, h->n, (int)h->dtype, K, h->tune_chunk, h->tune_unroll);
+    fprintf(f, "%d %d %d %d %d %d %d\n", h->m, h->n, (int)h->dtype, K, h->tune_chunk, h->tune_unroll, h->tune_bucket);
     fclose(f);
 }
 
@@ -197,7 +221,7 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     const int chunk = chunk_for(h, J, p->chunk);
     const int cpb = (J + chunk - 1) / chunk;
 
-    const Workspace lay = workspace_layout(h, batch, J, K, s_max, chunk);
+    const Workspace lay = workspace_layout(h, batch, J, K, s_max, chunk, p->dbg_samples != nullptr);
     char *ws;
     int rc = KERDOCK_OK;
     if (ext_ws) {
@@ -218,12 +242,12 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     float *svals = reinterpret_cast<float *>(ws + lay.svals);
     int *row_ws = reinterpret_cast<int *>(ws + lay.rows);
 
-    // kernel_ms slots: [0] stays 0 (the draws and coefficients are computed
-    // inside the gather kernel), [1] draws + gather, [2] select, [3] survivors
+    // kernel_ms slots: [0] grouping of the draws by basis (0 without it),
+    // [1] draws, coefficients + gather, [2] select, [3] survivors
     const bool timed = p->kernel_ms != nullptr;
     if (timed && !h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
-    if (timed) KD_HIP(hipEventRecord(h->ev[1], s));
+    if (timed) KD_HIP(hipEventRecord(h->ev[0], s));
     DGArgs dg{};
     dg.table = reinterpret_cast<const unsigned char *>(h->table);
     dg.col_bytes = h->pitch * (int)dtype_bytes(h->dtype);
@@ -246,10 +270,19 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     }
     dg.pitch = h->pitch;
     dg.partial = partial;
-    dg.dbg_samples = p->dbg_samples;
+    dg.bucket = use_bucket(h, J);
+    if (dg.bucket) {
+        dg.jlist = p->dbg_samples ? p->dbg_samples : reinterpret_cast<uint32_t *>(ws + lay.jlist);
+        dg.sorted = reinterpret_cast<uint32_t *>(ws + lay.sorted);
+        dg.perm = p->dbg_samples ? reinterpret_cast<int32_t *>(ws + lay.perm) : nullptr;
+    } else {
+        dg.dbg_samples = p->dbg_samples;
+    }
     dg.dbg_coef = p->dbg_coef;
     dg.active = active;
-    rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
+    if (dg.bucket) rc = launch_draw_sort(dg, batch, K, s);
+    if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
+    if (rc == KERDOCK_OK) rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
     SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, active};
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
@@ -261,8 +294,7 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     if (rc != KERDOCK_OK) return rc;
     if (timed) {
         KD_HIP(hipEventSynchronize(h->ev[4]));
-        p->kernel_ms[0] = 0.f;
-        for (int q = 1; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
+        for (int q = 0; q < 4; ++q) KD_HIP(hipEventElapsedTime(&p->kernel_ms[q], h->ev[q], h->ev[q + 1]));
     }
     if (p->dbg_survivors)
         KD_HIP(hipMemcpyAsync(p->dbg_survivors, surv, (size_t)batch * s_max * 4, hipMemcpyDeviceToDevice, s));
@@ -328,12 +360,19 @@ int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, 
         const size_t cc = std::min(c, J);
         need = std::max(need, (size_t)batch * K * ((J + cc - 1) / cc) * h->pitch * 4);
     }
-    int rc = ensure_workspace(h, need);
+    const size_t draws = align256((size_t)batch * J * K * 4);
+    need = align256(need);
+    int rc = ensure_workspace(h, need + 2 * draws);
     if (rc != KERDOCK_OK) return rc;
+    uint32_t *jlist = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h->ws) + need);
+    uint32_t *sorted = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(h->ws) + need + draws);
     if (!h->ev[0])
         for (int q = 0; q < 5; ++q) KD_HIP(hipEventCreate(&h->ev[q]));
     float best = 1e30f;
-    int bc = 512, bu = 8;
+    int bc = 512, bu = 8, bb = 0;
+    // grouping by basis is worth timing only with runs of several draws
+    const int nbk = (int64_t)J >= 2 * (int64_t)(h->d / 2 + 1) ? 2 : 1;
+    for (int bk = 0; bk < nbk; ++bk)
     for (int c : chunks) {
         const int chunk = std::min(c, J);
         if (c > J && c != chunks[0]) continue;
@@ -356,10 +395,14 @@ int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, 
             dg.tpc = gs.tpc;
             dg.pitch = h->pitch;
             dg.partial = reinterpret_cast<float *>(h->ws);
+            dg.bucket = bk;
+            dg.jlist = jlist;
+            dg.sorted = sorted;
             float tmin = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
                 KD_HIP(hipEventRecord(h->ev[0], s));
-                rc = launch_draw_gather(h->dtype, dg, batch, K, u, s);
+                rc = bk ? launch_draw_sort(dg, batch, K, s) : KERDOCK_OK;
+                if (rc == KERDOCK_OK) rc = launch_draw_gather(h->dtype, dg, batch, K, u, s);
                 if (rc != KERDOCK_OK) return rc;
                 KD_HIP(hipEventRecord(h->ev[1], s));
                 KD_HIP(hipEventSynchronize(h->ev[1]));
@@ -371,11 +414,13 @@ int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, 
                 best = tmin;
                 bc = chunk;
                 bu = u;
+                bb = bk;
             }
         }
     }
     h->tune_chunk = bc;
     h->tune_unroll = bu;
+    h->tune_bucket = bb;
     cache_store(h, K);
     if (best_chunk) *best_chunk = bc;
     if (best_unroll) *best_unroll = bu;

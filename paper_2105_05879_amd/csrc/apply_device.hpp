@@ -52,22 +52,36 @@ __device__ __forceinline__ uint32_t walsh32(uint32_t v) {
     return w;
 }
 
-// -------------------------------------------------- draws + gather (fused) --
-// One workgroup owns one chunk of the draws of one batch of one vector and
-// TILES x 4 KiB of every column (the whole column up to 16 KiB).
+// ------------------------------------------- draws, buckets and gather --
+// Three stages per batch of J draws of one vector.
 //
-// Phase 1, draws and coefficients.  Draw j of vector t is block floor(j/4)
-// of Philox4x64-10 at counter (floor(j/4), t0 + t, 0, 0), key (seed, 0),
-// word j mod 4, and l = floor(r L / 2^64).  The coefficient c = s_l^T x is,
-// for a Kerdock vector, a signed sum of x: lane `ln` holds x[e] for
+// Draws and buckets (draw_sort, one workgroup per (vector, batch)).  Draw j
+// of vector t is word j mod 4 of Philox4x64-10 at counter (floor(j/4),
+// t0 + t, 0, 0), key (seed, 0), and l = floor(r L / 2^64).  The draws of
+// the batch are sorted by their basis b = l >> k with a counting sort:
+// per-wave histograms of b in LDS, one scan over (basis, wave), then every
+// wave places its draws in drawing order, ranking equal bases within 64
+// draws by ballots over the bits of b.  The batch's draws thus come grouped
+// by basis, in drawing order within a basis; only the summation order of the
+// batch sum depends on this.
+//
+// Coefficients (draw_gather phase 1).  One workgroup owns `chunk`
+// consecutive sorted draws of one batch of one vector and TILES x 4 KiB of
+// every column (the whole column up to 16 KiB).  c = s_l^T x is, for a
+// Kerdock vector, a signed sum of x: lane `ln` holds x[e] for
 // e = (ln + 64 p) * 32 + q (q < 32), so that bit q of sign word (ln + 64 p)
 // of basis b is Q_b(e), and with w = (w_hi, w_lo) the Walsh sign of e is
-// parity((ln + 64 p) & w_hi) ^ parity(q & w_lo).  The sum is exact: x is
-// converted once to fixed point x_int = x 2^E with sum |x_int| <= 2^30, and
-// -x_int = (x_int ^ -1) + 1, so sum_q s_q x_q = sum_q (x_q ^ m_q) + popcount
-// of the negative signs, with m_q in {0, -1}; the only roundings are that of
-// x to the 2^-E grid and of the final integer to FP32.  An identity vector
-// gives sqrt(d) x[w] (zero for w >= n).  The (l, c) pairs go to LDS.
+// parity((ln + 64 p) & w_hi) ^ parity(q & w_lo).  The sums are exact: x is
+// converted once to fixed point x_int = x 2^E with sum |x_int| <= 2^30, so
+// every partial sum is an exact int32; the only roundings are that of x to
+// the 2^-E grid and of the final integer to FP32.  A run of at least
+// BUCKET_MIN draws of one Kerdock basis (Lemma 8's per-basis transform)
+// forms y = sigma_b x once and its 32-point Walsh-Hadamard transform
+// Y[v] = sum_q y_q (-1)^{q.v} per lane, so a draw costs one register pick
+// Y[w_lo], a lane sign and the wave sum; other draws sum directly,
+// sum_q s_q x_q = sum_q (x_q ^ m_q) + popcount of the negative signs with
+// m_q in {0, -1}.  Both give the same integer.  An identity vector gives
+// sqrt(d) x[w] (zero for w >= n).  The (l, c) pairs go to LDS.
 //
 // Phase 2, the hot loop: stream the columns T[l] and accumulate c T[l] in
 // FP32 registers; each thread owns TILES x 16 bytes (4 FP32, 8 BF16 or 16
@@ -129,8 +143,12 @@ struct DGArgs {
     int64_t t0;               // stream position of row 0 when t0_dev is NULL
     int N, J, chunk, chunks_per_batch, groups, tpc, pitch;
     float *partial;           // [batch][K chunks_per_batch][pitch]
-    uint32_t *dbg_samples;    // optional [batch][N]
-    float *dbg_coef;          // optional [batch][N]
+    int bucket;               // 1: draws grouped by basis (draw_sort ran), 0: drawn here in order
+    uint32_t *jlist;          // bucket: [batch][N] draws in drawing order (written by draw_sort)
+    uint32_t *sorted;         // bucket: [batch][N] draws of each batch grouped by basis
+    int32_t *perm;            // bucket, optional [batch][N]: draw index j of each sorted entry
+    uint32_t *dbg_samples;    // no bucket, optional [batch][N] draws
+    float *dbg_coef;          // optional [batch][N] (with bucket it needs perm)
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
 };
 
@@ -164,119 +182,403 @@ __device__ __forceinline__ void fixed_point(const float *__restrict__ x, int n, 
         for (int q = 0; q < 32; ++q) xi[p][q] = finite ? (int)rintf(xf[p][q] * up) : 0;
 }
 
-// Draws jbeg .. jbeg + cnt - 1 (cnt <= MAX_CHUNK) of the Philox stream with
-// counter words (floor(j/4), pos, word2, 0) and their coefficients s_l^T x,
-// into s_ell / s_coef; all four waves of the workgroup take part, and the
-// caller synchronises before reading them.  The method is described at
-// draw_gather below.
-template <int P>
-__device__ __forceinline__ void draws_coefs(const float *__restrict__ x, int n, int k, int64_t L,
-                                            const uint32_t *__restrict__ signs, uint64_t seed, uint64_t pos,
-                                            uint64_t word2, int jbeg, int cnt, uint32_t *s_ell,
-                                            float *s_coef) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    {
-        const int d = 1 << k;
-        const int words = d >= 32 ? d / 32 : 1;
-        int xi[P][32];
-        int E2;
-        bool finite;
-        fixed_point<P>(x, n, lane, xi, E2, finite);
-        const float down = ldexpf(1.0f, -E2);
-        const float sqrt_d = sqrtf((float)d);
+// ------------------------------------------------------------ draw_sort --
+constexpr int SORT_THREADS = 256;
 
-        // the four waves take equal runs of the chunk's draws (a multiple of
-        // four each), 64 at a time, one draw per lane for the Philox block
-        const int per = ((cnt + 3) / 4 + 3) & ~3;
-        const int rend = min(cnt, (wave + 1) * per);
-        for (int r0 = wave * per; r0 < rend; r0 += 64) {
-            const int jn = min(64, rend - r0);
-            uint32_t my_l = 0;
-            if (lane < jn) {
-                const int j = jbeg + r0 + lane;
-                uint64_t c4[4] = {(uint64_t)(j >> 2), pos, word2, 0};
-                philox4x64_10(c4, seed, 0);
-                const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
-                my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
-            }
-            float my_c = 0.f;
-            for (int jj0 = 0; jj0 < jn; jj0 += 4) {
-                uint32_t lq[4], sw[4][P];
+// exclusive scan over the SORT_THREADS threads of a workgroup (sh holds
+// SORT_THREADS / 64 + 1 ints); *total receives the sum
+__device__ __forceinline__ int sort_block_scan(int v, int *total, int *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = v;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    lq[u] = __builtin_amdgcn_readlane(my_l, min(jj0 + u, jn - 1));
-                    const uint32_t b = lq[u] >> k;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, off);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) sh[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < SORT_THREADS / 64; ++w) {
+            const int c = sh[w];
+            sh[w] = run;
+            run += c;
+        }
+        sh[SORT_THREADS / 64] = run;
+    }
+    __syncthreads();
+    const int res = sh[wave] + incl - v;
+    *total = sh[SORT_THREADS / 64];
+    __syncthreads();
+    return res;
+}
+
+// Draws of batch kb of vector t into a.jlist (drawing order) and a.sorted
+// (grouped by basis, drawing order within a basis), and with a.perm the draw
+// index of every sorted entry.  cur: LDS [(d/2 + 1) * 4] counters, indexed
+// basis * 4 + wave; sh: SORT_THREADS / 64 + 1 ints.
+__device__ __forceinline__ void draw_sort(const DGArgs &a, int t, int kb, uint32_t *cur, int *sh) {
+    if (a.active && !a.active[t]) return;      // uniform over the workgroup
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = a.k, nbin = (1 << (k - 1)) + 1, J = a.J;
+    const int64_t t0 = a.t0_dev ? *a.t0_dev : a.t0;
+    const uint64_t pos = (uint64_t)(t0 + t);
+    const uint64_t L = (uint64_t)a.L;
+    const int J0 = kb * J;
+    uint32_t *jl = a.jlist + (size_t)t * a.N + J0;
+    uint32_t *so = a.sorted + (size_t)t * a.N + J0;
+    int32_t *pm = a.perm ? a.perm + (size_t)t * a.N + J0 : nullptr;
+    for (int i = threadIdx.x; i < nbin * 4; i += SORT_THREADS) cur[i] = 0;
+    __syncthreads();
+
+    // pass 1: Philox blocks c (draws 4c .. 4c + 3) of the batch, a
+    // contiguous range of blocks per wave, one block per lane; histogram of
+    // the bases per wave
+    const int c_lo = J0 >> 2, c_hi = (J0 + J + 3) >> 2;
+    const int bpw = (c_hi - c_lo + 3) / 4;
+    const int wb = min(c_hi, c_lo + wave * bpw), we = min(c_hi, wb + bpw);
+    for (int c0 = wb; c0 < we; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < we) {
+            uint64_t w4[4] = {(uint64_t)c, pos, 0, 0};
+            philox4x64_10(w4, a.seed, 0);
 #pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const int word = lane + 64 * p;
-                        sw[u][p] = ((int)b < d / 2 && word < words) ? signs[(size_t)b * words + word] : 0u;
-                    }
+            for (int u = 0; u < 4; ++u) {
+                const int j = 4 * c + u;
+                if (j >= J0 && j < J0 + J) {
+                    const uint32_t l = (uint32_t)__umul64hi(w4[u], L);
+                    jl[j - J0] = l;
+                    atomicAdd(&cur[(l >> k) * 4 + wave], 1u);
                 }
-                // per-lane partial sums of the four draws, then one
-                // transposed butterfly for all four: bits 5 and 4 of the lane
-                // pick the draw, bits 3..0 finish the sums (exact integers)
-                int part[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t w = lq[u] & (uint32_t)(d - 1);
-                    const uint32_t wlo = walsh32(w & 31u);
-                    int acc = 0;
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const uint32_t word = (uint32_t)(lane + 64 * p);
-                        if ((int)word < words) {
-                            const uint32_t par = __popc(word & (w >> 5)) & 1u;
-                            const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
-#pragma unroll
-                            for (int q = 0; q < 32; ++q)
-                                acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
-                            acc += __popc(mask);
-                        }
-                    }
-                    part[u] = acc;
-                }
-                const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
-                const int k0 = (h5 ? part[2] : part[0]) + __shfl_xor(h5 ? part[0] : part[2], 32);
-                const int k1 = (h5 ? part[3] : part[1]) + __shfl_xor(h5 ? part[1] : part[3], 32);
-                int z = (h4 ? k1 : k0) + __shfl_xor(h4 ? k0 : k1, 16);
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (jj0 + u >= jn) break;
-                    const uint32_t b = lq[u] >> k, w = lq[u] & (uint32_t)(d - 1);
-                    float c;
-                    if ((int)b == d / 2) {
-                        c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
-                    } else {
-                        const int tot = __builtin_amdgcn_readlane(z, ((u >> 1) << 5) | ((u & 1) << 4));
-                        c = finite ? (float)tot * down : __builtin_nanf("");
-                    }
-                    if (lane == jj0 + u) my_c = c;
-                }
-            }
-            if (lane < jn) {
-                s_ell[r0 + lane] = my_l;
-                s_coef[r0 + lane] = my_c;
             }
         }
     }
+    __syncthreads();
 
+    // start of every (basis, wave) range: exclusive scan in (basis, wave) order
+    {
+        const int tot = nbin * 4;
+        const int per = (tot + SORT_THREADS - 1) / SORT_THREADS;
+        const int i0 = min(tot, (int)threadIdx.x * per), i1 = min(tot, i0 + per);
+        int local = 0;
+        for (int i = i0; i < i1; ++i) local += (int)cur[i];
+        int total;
+        int run = sort_block_scan(local, &total, sh);
+        for (int i = i0; i < i1; ++i) {
+            const int c = (int)cur[i];
+            cur[i] = (uint32_t)run;
+            run += c;
+        }
+    }
+    __syncthreads();
+
+    // pass 2: every wave places its draws (the ones it drew, re-read in
+    // drawing order, 64 at a time); lanes with equal bases are ranked by the
+    // ballots of the bits of b, and the lowest of them advances the counter
+    const int rb = max(4 * wb, J0) - J0, re = min(4 * we, J0 + J) - J0;
+    constexpr int PF = 8;              // steps whose draws are loaded at once
+    uint32_t lbuf[PF];
+    for (int r0 = rb; r0 < re; r0 += 64) {
+        const int step = ((r0 - rb) >> 6) % PF;
+        if (step == 0)
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+                const int rr = r0 + 64 * u + lane;
+                lbuf[u] = rr < re ? jl[rr] : 0u;
+            }
+        const int r = r0 + lane;
+        const bool valid = r < re;
+        uint32_t l = lbuf[0];
+#pragma unroll
+        for (int u = 1; u < PF; ++u)
+            if (step == u) l = lbuf[u];
+        const uint32_t b = l >> k;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < k; ++bit) {
+            const bool on = (b >> bit) & 1u;
+            const uint64_t bal = __ballot(on);
+            peers &= on ? bal : ~bal;
+        }
+        if (valid) {
+            const int rank = __popcll(peers & ((1ull << lane) - 1ull));
+            const uint32_t base = cur[b * 4 + wave];
+            so[base + rank] = l;
+            if (pm) pm[base + rank] = J0 + r;
+            if (rank == 0) cur[b * 4 + wave] = base + (uint32_t)__popcll(peers);
+        }
+    }
 }
+
+// ------------------------------------------------------- coefficients --
+// Runs of at least this many draws of one Kerdock basis use the per-basis
+// transform; shorter runs sum directly (the transform costs about as much as
+// three direct sums).
+constexpr int BUCKET_MIN = 4;
+
+// x in fixed point in LDS, shared by the waves of a workgroup: word p of
+// lane `lane` (elements (lane + 64 p) 32 + q, q < 32) as eight 16-byte
+// pieces, piece j at ((p 8 + j) 64 + lane) 16 bytes (consecutive lanes,
+// consecutive pieces: no bank conflicts).
+constexpr int XI_INTS_PER_P = 32 * 64;
+
+__device__ __forceinline__ void load_xi_word(const int *s_xi, int p, int lane, int (&y)[32]) {
+    const int4 *src = reinterpret_cast<const int4 *>(s_xi) + (size_t)p * 8 * 64 + lane;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int4 v = src[j * 64];
+        y[4 * j] = v.x;
+        y[4 * j + 1] = v.y;
+        y[4 * j + 2] = v.z;
+        y[4 * j + 3] = v.w;
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void load_xi(const int *s_xi, int lane, int (&xi)[P][32]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) load_xi_word(s_xi, p, lane, xi[p]);
+}
+
+// fixed_point by one wave, written straight to LDS in the layout above;
+// s_fx receives E2 and finite (0 / 1)
+template <int P>
+__device__ __forceinline__ void fixed_point_lds(const float *__restrict__ x, int n, int lane, int *s_xi, int *s_fx) {
+    float xf[P][32];
+    float asum = 0.f;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int e = (lane + 64 * p) * 32 + q;
+            xf[p][q] = e < n ? x[e] : 0.f;
+            asum += fabsf(xf[p][q]);
+        }
+    asum = wave_sum_f32(asum);
+    // the same scale as fixed_point: 2^E2 with asum 2^E2 <= 2^30
+    const bool finite = asum < INFINITY;
+    int E2 = 0;
+    if (finite && asum > 0.f) E2 = 29 - ((int)((__float_as_uint(asum) >> 23) & 0xFF) - 127);
+    E2 = max(-120, min(E2, 120));
+    const float up = ldexpf(1.0f, E2);
+    int4 *dst = reinterpret_cast<int4 *>(s_xi) + lane;
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = finite ? (int)rintf(xf[p][4 * j + c] * up) : 0;
+            dst[(p * 8 + j) * 64] = make_int4(v[0], v[1], v[2], v[3]);
+        }
+    if (lane == 0) {
+        s_fx[0] = E2;
+        s_fx[1] = finite ? 1 : 0;
+    }
+}
+
+// Direct signed sums of the draws at LDS positions list[0 .. cnt), or
+// base .. base + cnt - 1 when list is NULL (one
+// wave; four draws at a time so that the sign-word loads overlap).
+template <int P>
+__device__ __forceinline__ void direct_coefs(const int (&xi)[P][32], float down, bool finite,
+                                             const float *__restrict__ x, int n, int k,
+                                             const uint32_t *__restrict__ signs, const int *list, int base, int cnt,
+                                             const uint32_t *s_ell, float *s_coef) {
+    const int lane = threadIdx.x & 63;
+    const int d = 1 << k;
+    const int words = d >= 32 ? d / 32 : 1;
+    const float sqrt_d = sqrtf((float)d);
+    for (int jj0 = 0; jj0 < cnt; jj0 += 4) {
+        uint32_t lq[4], sw[4][P];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int jp = min(jj0 + u, cnt - 1);
+            lq[u] = s_ell[list ? list[jp] : base + jp];
+            const uint32_t b = lq[u] >> k;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int word = lane + 64 * p;
+                sw[u][p] = ((int)b < d / 2 && word < words) ? signs[(size_t)b * words + word] : 0u;
+            }
+        }
+        // per-lane partial sums of the four draws, then one transposed
+        // butterfly for all four: bits 5 and 4 of the lane pick the draw,
+        // bits 3..0 finish the sums (exact integers)
+        int part[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t w = lq[u] & (uint32_t)(d - 1);
+            const uint32_t wlo = walsh32(w & 31u);
+            int acc = 0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint32_t word = (uint32_t)(lane + 64 * p);
+                if ((int)word < words) {
+                    const uint32_t par = __popc(word & (w >> 5)) & 1u;
+                    const uint32_t mask = sw[u][p] ^ wlo ^ (0u - par);
+#pragma unroll
+                    for (int q = 0; q < 32; ++q) acc += xi[p][q] ^ (int)__builtin_amdgcn_sbfe(mask, q, 1);
+                    acc += __popc(mask);
+                }
+            }
+            part[u] = acc;
+        }
+        const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+        const int k0 = (h5 ? part[2] : part[0]) + __shfl_xor(h5 ? part[0] : part[2], 32);
+        const int k1 = (h5 ? part[3] : part[1]) + __shfl_xor(h5 ? part[1] : part[3], 32);
+        int z = (h4 ? k1 : k0) + __shfl_xor(h4 ? k0 : k1, 16);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (jj0 + u >= cnt) break;
+            const uint32_t b = lq[u] >> k, w = lq[u] & (uint32_t)(d - 1);
+            float c;
+            if ((int)b == d / 2) {
+                c = ((int)w < n) ? sqrt_d * x[w] : 0.f;
+            } else {
+                const int tot = __builtin_amdgcn_readlane(z, ((u >> 1) << 5) | ((u & 1) << 4));
+                c = finite ? (float)tot * down : __builtin_nanf("");
+            }
+            if (lane == 0) s_coef[list ? list[jj0 + u] : base + jj0 + u] = c;
+        }
+    }
+}
+
+// A run of cnt >= 1 draws of Kerdock basis b at LDS positions i0 .. i0 + cnt
+// (one wave): y = sigma_b x, Y = the 32-point Walsh-Hadamard transform of
+// each lane's word, then c = sum over lanes and words of
+// (-1)^{parity(word & w_hi)} Y[w_lo] for each draw.
+template <int P>
+__device__ __forceinline__ void transform_run(const int *s_xi, float down, bool finite, int k, uint32_t b,
+                                              const uint32_t *__restrict__ signs, int i0, int cnt,
+                                              const uint32_t *s_ell, float *s_coef) {
+    typedef int i32x32 __attribute__((ext_vector_type(32)));
+    const int lane = threadIdx.x & 63;
+    const int d = 1 << k;
+    const int words = d >= 32 ? d / 32 : 1;
+    i32x32 Y[P];        // vectors, so that a wave-uniform index picks a register
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int word = lane + 64 * p;
+        const uint32_t sw = word < words ? signs[(size_t)b * words + word] : 0u;
+        int y[32];
+        load_xi_word(s_xi, p, lane, y);
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+            const int m = (int)__builtin_amdgcn_sbfe(sw, q, 1);
+            y[q] = (y[q] ^ m) - m;
+        }
+#pragma unroll
+        for (int h = 1; h < 32; h <<= 1)
+#pragma unroll
+            for (int q = 0; q < 32; ++q)
+                if ((q & h) == 0) {
+                    const int u = y[q], v = y[q + h];
+                    y[q] = u + v;
+                    y[q + h] = u - v;
+                }
+#pragma unroll
+        for (int q = 0; q < 32; ++q) Y[p][q] = y[q];
+    }
+    for (int jj0 = 0; jj0 < cnt; jj0 += 4) {
+        int part[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t l = __builtin_amdgcn_readfirstlane(s_ell[i0 + min(jj0 + u, cnt - 1)]);
+            const uint32_t w = l & (uint32_t)(d - 1);
+            const int wlo = (int)__builtin_amdgcn_readfirstlane(w & 31u);
+            int acc = 0;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const uint32_t word = (uint32_t)(lane + 64 * p);
+                const int neg = -(int)(__popc(word & (w >> 5)) & 1u);
+                acc += (Y[p][wlo] ^ neg) - neg;
+            }
+            part[u] = acc;
+        }
+        const bool h5 = (lane & 32) != 0, h4 = (lane & 16) != 0;
+        const int k0 = (h5 ? part[2] : part[0]) + __shfl_xor(h5 ? part[0] : part[2], 32);
+        const int k1 = (h5 ? part[3] : part[1]) + __shfl_xor(h5 ? part[1] : part[3], 32);
+        int z = (h4 ? k1 : k0) + __shfl_xor(h4 ? k0 : k1, 16);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) z += __shfl_xor(z, off);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (jj0 + u >= cnt) break;
+            const int tot = __builtin_amdgcn_readlane(z, ((u >> 1) << 5) | ((u & 1) << 4));
+            if (lane == 0) s_coef[i0 + jj0 + u] = finite ? (float)tot * down : __builtin_nanf("");
+        }
+    }
+}
+
+// Coefficients of the cnt (<= MAX_CHUNK) sorted draws in s_ell into s_coef;
+// the four waves take equal contiguous runs of positions, split them into
+// runs of one basis, transform the long Kerdock runs and collect the other
+// positions in s_list (same positions, so the waves' lists never overlap)
+// for the direct sums.  The caller synchronises before and after.
+template <int P>
+__device__ __forceinline__ void bucket_coefs(const float *__restrict__ x, int n, int k,
+                                             const uint32_t *__restrict__ signs, int cnt, const uint32_t *s_ell,
+                                             float *s_coef, int *s_list, const int *s_xi, int E2, bool finite) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int d = 1 << k;
+    const float down = ldexpf(1.0f, -E2);
+    const int per = ((cnt + 3) / 4 + 3) & ~3;
+    const int r0 = min(cnt, wave * per), r1 = min(cnt, r0 + per);
+    int nd = 0;
+    for (int i = r0; i < r1;) {
+        const uint32_t b = __builtin_amdgcn_readfirstlane(s_ell[i] >> k);
+        int run = 0;
+        for (;;) {
+            const int q = i + run + lane;
+            const uint64_t same = __ballot(q < r1 && (s_ell[q] >> k) == b);
+            const int c = same == ~0ull ? 64 : __ffsll((long long)~same) - 1;
+            run += c;
+            if (c < 64) break;
+        }
+        if ((int)b < d / 2 && run >= BUCKET_MIN) {
+            transform_run<P>(s_xi, down, finite, k, b, signs, i, run, s_ell, s_coef);
+        } else {
+            for (int q = lane; q < run; q += 64) s_list[r0 + nd + q] = i + q;
+            nd += run;
+        }
+        i += run;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (nd > 0) {
+        int xi[P][32];
+        load_xi<P>(s_xi, lane, xi);
+        direct_coefs<P>(xi, down, finite, x, n, k, signs, s_list + r0, 0, nd, s_ell, s_coef);
+    }
+}
+
+// LDS of one draws + gather workgroup: the draws, coefficients, direct-sum
+// list and fixed-point x of phase 1, then (aliasing them once phase 2 has
+// read the last pair) the group sums of short columns.
+template <int DT, bool GROUPED, int P> struct DGSmem {
+    static constexpr size_t PHASE1 = 3 * MAX_CHUNK * 4 + (size_t)P * XI_INTS_PER_P * 4 + 16;
+    static constexpr size_t RED = GROUPED ? (size_t)GATHER_THREADS * Elems<DT>::N * 4 : 0;
+    static constexpr size_t BYTES = PHASE1 > RED ? PHASE1 : RED;
+};
 
 template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
 __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int seg, int nchunks,
-                                            uint32_t *s_ell, float *s_coef, float *red) {
+                                            unsigned char *smem) {
+    uint32_t *s_ell = reinterpret_cast<uint32_t *>(smem);
+    float *s_coef = reinterpret_cast<float *>(smem + MAX_CHUNK * 4);
+    int *s_list = reinterpret_cast<int *>(smem + 2 * MAX_CHUNK * 4);
+    int *s_xi = reinterpret_cast<int *>(smem + 3 * MAX_CHUNK * 4);
+    int *s_fx = s_xi + P * XI_INTS_PER_P;             // E2, finite
+    float *red = reinterpret_cast<float *>(smem);
     const unsigned char *__restrict__ table = a.table;
     const int col_bytes = a.col_bytes, n = a.n, k = a.k, N = a.N, J = a.J, chunk = a.chunk;
     const int chunks_per_batch = a.chunks_per_batch, groups = a.groups, tpc = a.tpc, pitch = a.pitch;
     const float *__restrict__ X = a.X;
-    const int64_t L = a.L;
     const uint32_t *__restrict__ signs = a.signs;
-    const uint64_t seed = a.seed;
-    const int64_t t0 = a.t0_dev ? *a.t0_dev : a.t0;
     float *__restrict__ partial = a.partial;
-    uint32_t *__restrict__ dbg_samples = a.dbg_samples;
     float *__restrict__ dbg_coef = a.dbg_coef;
     constexpr int E = Elems<DT>::N;
     if (a.active && !a.active[t]) return;      // uniform over the workgroup
@@ -285,13 +587,52 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     const int cnt = min(chunk, (kb + 1) * J - jbeg);
 
     // ---------------------------------------------------------- phase 1
-    draws_coefs<P>(X + (size_t)t * n, n, k, L, signs, seed, (uint64_t)(t0 + t), 0, jbeg, cnt, s_ell, s_coef);
-    __syncthreads();
-    if (dbg_samples && seg == 0)
-        for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS) {
-            dbg_samples[(size_t)t * N + jbeg + r] = s_ell[r];
-            dbg_coef[(size_t)t * N + jbeg + r] = s_coef[r];
+    const int per = ((cnt + 3) / 4 + 3) & ~3;          // the waves' runs of positions
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r0 = min(cnt, wave * per), r1 = min(cnt, r0 + per);
+    if (a.bucket) {
+        // the batch's draws grouped by basis (draw_sort), x in fixed point
+        // shared through LDS by wave 0, then the four waves' runs
+        const uint32_t *src = a.sorted + (size_t)t * N + jbeg;
+        for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS) s_ell[r] = src[r];
+        if (threadIdx.x < 64) fixed_point_lds<P>(X + (size_t)t * n, n, threadIdx.x, s_xi, s_fx);
+        __syncthreads();
+        bucket_coefs<P>(X + (size_t)t * n, n, k, signs, cnt, s_ell, s_coef, s_list, s_xi, s_fx[0], s_fx[1] != 0);
+    } else {
+        // every wave on its own run of positions: x in fixed point (in
+        // registers), draw j = jbeg + r as word j mod 4 of Philox4x64-10 at
+        // counter (floor(j/4), t0 + t, 0, 0), key (seed, 0), l = floor(r L /
+        // 2^64), and the direct sums
+        int xi[P][32];
+        int E2;
+        bool finite;
+        fixed_point<P>(X + (size_t)t * n, n, lane, xi, E2, finite);
+        const int64_t t0 = a.t0_dev ? *a.t0_dev : a.t0;
+        for (int r = r0 + lane; r < r1; r += 64) {
+            const int j = jbeg + r;
+            uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + t), 0, 0};
+            philox4x64_10(c4, a.seed, 0);
+            const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
+            s_ell[r] = (uint32_t)__umul64hi(rr, (uint64_t)a.L);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        direct_coefs<P>(xi, ldexpf(1.0f, -E2), finite, X + (size_t)t * n, n, k, signs, nullptr, r0, r1 - r0, s_ell,
+                        s_coef);
+    }
+    __syncthreads();
+    if (dbg_coef && seg == 0) {
+        if (a.bucket) {
+            for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS)
+                dbg_coef[(size_t)t * N + a.perm[(size_t)t * N + jbeg + r]] = s_coef[r];
+        } else {
+            for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS) {
+                a.dbg_samples[(size_t)t * N + jbeg + r] = s_ell[r];
+                dbg_coef[(size_t)t * N + jbeg + r] = s_coef[r];
+            }
+        }
+    }
 
     // ---------------------------------------------------------- phase 2
     const int g = GROUPED ? (int)threadIdx.x / tpc : 0;
@@ -347,6 +688,7 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     }
 
     if constexpr (GROUPED) {
+        __syncthreads();               // every (l, c) pair read: red reuses their LDS
 #pragma unroll
         for (int e = 0; e < E; ++e) red[e * GATHER_THREADS + threadIdx.x] = acc[0][e];
         __syncthreads();

@@ -6,12 +6,16 @@ namespace kd {
 
 template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
 __global__ __launch_bounds__(GATHER_THREADS) void k_draw_gather(DGArgs a) {
-    constexpr int E = Elems<DT>::N;
-    __shared__ uint32_t s_ell[MAX_CHUNK];
-    __shared__ float s_coef[MAX_CHUNK];
-    __shared__ float red[GROUPED ? GATHER_THREADS * E : 1];
-    draw_gather<DT, TILES, UNROLL, GROUPED, P>(a, blockIdx.z, blockIdx.x, blockIdx.y, gridDim.x, s_ell,
-                                               s_coef, red);
+    __shared__ __align__(16) unsigned char smem[DGSmem<DT, GROUPED, P>::BYTES];
+    draw_gather<DT, TILES, UNROLL, GROUPED, P>(a, blockIdx.z, blockIdx.x, blockIdx.y, gridDim.x, smem);
+}
+
+// grid (K, batch): draws of batch blockIdx.x of vector blockIdx.y, grouped
+// by basis (dynamic LDS: (d/2 + 1) * 4 counters)
+__global__ __launch_bounds__(SORT_THREADS) void k_draw_sort(DGArgs a) {
+    extern __shared__ uint32_t cur[];
+    __shared__ int sh[SORT_THREADS / 64 + 1];
+    draw_sort(a, blockIdx.y, blockIdx.x, cur, sh);
 }
 
 template <int KMAX>
@@ -141,16 +145,6 @@ __global__ __launch_bounds__(SELECT_THREADS) void k_topc_logits(const float *__r
     select_top(key, m, c, 0u, cand + (size_t)t * c, ncand + t, hist, scan_sh, sel_state);
 }
 
-// fall back when the verified energy sum_{i in C} (a_i.x)^2 falls short of
-// the exact energy |Ax|^2 by more than tol (NaN also falls back)
-__global__ void k_fallback_flags(const float *__restrict__ E, const float *__restrict__ vsum2, int B, float tol,
-                                 int32_t *__restrict__ flags) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= B) return;
-    const float gap = E[t] - vsum2[t];
-    flags[t] = (gap <= tol) ? 0 : 1;
-}
-
 // -------------------------------------------------------------- launchers --
 
 int launch_topc_logits(const float *Z, int B, int m, int c, int32_t *cand, int32_t *ncand, hipStream_t s) {
@@ -158,13 +152,6 @@ int launch_topc_logits(const float *Z, int B, int m, int c, int32_t *cand, int32
     KD_LAUNCH("k_topc_logits");
     return KERDOCK_OK;
 }
-
-int launch_fallback_flags(const float *E, const float *vsum2, int B, float tol, int32_t *flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_fallback_flags, dim3((B + 255) / 256), dim3(256), 0, s, E, vsum2, B, tol, flags);
-    KD_LAUNCH("k_fallback_flags");
-    return KERDOCK_OK;
-}
-
 
 GatherShape gather_shape(kerdock_dtype dt, int pitch, long long work) {
     GatherShape g;
@@ -219,6 +206,15 @@ static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const DGArgs 
         if (unroll <= 2) launch_dg<DT, 4, 2, false>(grid, a, s);
         else launch_dg<DT, 4, 4, false>(grid, a, s);
     }
+}
+
+size_t sort_lds_bytes(int k) { return (size_t)((1 << (k - 1)) + 1) * 4 * sizeof(uint32_t); }
+
+int launch_draw_sort(const DGArgs &a, int batch, int K, hipStream_t s) {
+    if (batch > 65535) return fail(KERDOCK_ERR_INVALID_ARG, "batch above 65535 (grid y dimension of the draw sort)");
+    hipLaunchKernelGGL(k_draw_sort, dim3(K, batch), dim3(SORT_THREADS), sort_lds_bytes(a.k), s, a);
+    KD_LAUNCH("k_draw_sort");
+    return KERDOCK_OK;
 }
 
 int launch_draw_gather(kerdock_dtype dt, const DGArgs &a, int batch, int K, int unroll, hipStream_t s) {

@@ -10,6 +10,8 @@
 // Layout in HBM: column l = b d + w is `pitch` contiguous elements (rows
 // i = 0..pitch-1, rows >= m are zero), so that the streaming step reads one
 // contiguous column per draw.
+#include <stdlib.h>
+
 #include "common.hpp"
 
 namespace kd {
@@ -247,6 +249,170 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
     }
 }
 
+// ------------------------------------------------- table build, d >= 256 --
+// The same transform without LDS traffic in the butterflies, in workgroups of
+// ROWS2 waves (two workgroups per CU, so that one's loads and stores overlap
+// the other's arithmetic).  Wave r holds row i0 + r, lane l and register q
+// holding the input element x = q 64 + (l ^ 15):
+//   * register bits (x bits 6..k-1): butterflies inside each lane;
+//   * lane bits 0..3 (xor 1, 2, 4, 8): the partner value arrives by DPP
+//     (quad_perm, row_half_mirror + quad_perm, row_ror:8) and every lane
+//     computes v + s p with s = -1 in the upper lane of the pair, i.e. the
+//     upper lanes hold the negated difference.  Across the four stages this
+//     multiplies output w by (-1)^{w . 15}, which the input order x ^ 15
+//     cancels exactly (H[w][x ^ 15] = (-1)^{w . 15} H[w][x]);
+//   * lane bits 4 and 5: v_permlane16_swap / v_permlane32_swap exchange lane
+//     bit 4 (5) with register bit 0 (1), after which the pair sits in one
+//     lane and the butterfly is local.
+// Output w of register q in lane l:
+//   w = (l & 15) | (q & 1) << 4 | (q >> 1 & 1) << 5 | (l >> 4 & 1) << 6 |
+//       (l >> 5 & 1) << 7 | (q >> 2) << 8.
+// Staging: chunks of up to 1024 columns = register bits 2.. fixed, as [column]
+// [row] with a row pitch of ROWS2 + 1 and 16 empty column slots after every
+// 64 columns (the four 16-lane groups of a write land on distinct banks).
+// The barriers around the staging wait for LDS only: stores to the table
+// need not complete before the next chunk.
+constexpr int ROWS2 = 8;
+
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int LOGD> __device__ __forceinline__ void fwht_wave2(float *v) {
+    constexpr int D = 1 << LOGD;
+    constexpr int R = D / 64;
+    const int lane = threadIdx.x & 63;
+    // register bits
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (q & h) continue;
+            const float a = v[q], b = v[q + h];
+            v[q] = a + b;
+            v[q + h] = a - b;
+        }
+    // lane bits 0..3 by DPP: v + s p, s = -1 in the upper lane
+    const float s1 = (lane & 1) ? -1.f : 1.f, s2 = (lane & 2) ? -1.f : 1.f;
+    const float s4 = (lane & 4) ? -1.f : 1.f, s8 = (lane & 8) ? -1.f : 1.f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = fmaf(dpp_f<0xB1>(v[q]), s1, v[q]);                  // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = fmaf(dpp_f<0x4E>(v[q]), s2, v[q]);                  // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = fmaf(dpp_f<0x1B>(dpp_f<0x141>(v[q])), s4, v[q]);   // half_mirror, [3,2,1,0]
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = fmaf(dpp_f<0x128>(v[q]), s8, v[q]);                 // row_ror:8
+    // lane bit 4 <-> register bit 0, then the butterfly in the lane
+#pragma unroll
+    for (int q = 0; q < R; q += 2) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[q]), __float_as_uint(v[q + 1]), false,
+                                                        false);
+        const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
+        v[q] = a + b;
+        v[q + 1] = a - b;
+    }
+    // lane bit 5 <-> register bit 1
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (q & 2) continue;
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[q]), __float_as_uint(v[q + 2]), false,
+                                                        false);
+        const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
+        v[q] = a + b;
+        v[q + 2] = a - b;
+    }
+}
+
+template <int LOGD, int DT>
+__global__ __launch_bounds__(ROWS2 * 64) void k_table_build2(const float *__restrict__ A, int m, int n, int pitch,
+                                                              const uint32_t *__restrict__ signs,
+                                                              const float *__restrict__ scales,
+                                                              void *__restrict__ table, int strips, int xcd_map) {
+    constexpr int D = 1 << LOGD;
+    constexpr int R = D / 64;
+    constexpr int WORDS = D / 32;
+    constexpr int COLS = D < STAGE_COLS ? D : STAGE_COLS;
+    constexpr int QC = COLS / 64;                       // registers per chunk
+    constexpr int P2 = ROWS2 + 1;
+    constexpr int SLOTS = COLS + 16 * (COLS / 64);
+    constexpr int THREADS = ROWS2 * 64;
+    __shared__ float stage[SLOTS * P2];
+    __shared__ uint32_t sbits[WORDS];
+
+    int g = blockIdx.x, b, strip;
+    if (xcd_map) {
+        const int per_xcd = strips / 8;
+        const int xcd = g & 7, qq = g >> 3;
+        strip = xcd * per_xcd + qq % per_xcd;
+        b = qq / per_xcd;
+    } else {
+        strip = g % strips;
+        b = g / strips;
+    }
+    const int i0 = strip * ROWS2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = i0 + wave;
+
+    for (int t = threadIdx.x; t < WORDS; t += THREADS) sbits[t] = signs[(size_t)b * WORDS + t];
+    __syncthreads();
+
+    // signed, zero-padded row in the order x = q 64 + (lane ^ 15)
+    float v[R];
+    const int rowc = row < m ? row : m - 1;
+    const int lx = lane ^ 15;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int x = q * 64 + lx;
+        const int xc = x < n ? x : n - 1;
+        const float a = A[(size_t)rowc * n + xc];
+        const uint32_t bit = (sbits[x >> 5] >> (x & 31)) & 1u;
+        v[q] = (row < m && x < n) ? (bit ? -a : a) : 0.f;
+    }
+    fwht_wave2<LOGD>(v);
+
+    using S = Store<DT>;
+    constexpr int PACK = S::ROWS;                       // rows per 32-bit store
+    constexpr int TPC = ROWS2 / PACK;                   // threads per column
+    constexpr int CPP = THREADS / TPC;                  // columns per pass
+    float scale[PACK];
+    const int my_rows = (threadIdx.x % TPC) * PACK;
+#pragma unroll
+    for (int r = 0; r < PACK; ++r) scale[r] = scales[i0 + my_rows + r];
+    uint32_t *out32 = reinterpret_cast<uint32_t *>(table);
+    const size_t col_words = (size_t)pitch * (DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1) / 4;
+    // column-local index of register j of a chunk in this lane, and its slot
+    const int wl_lane = (lane & 15) | ((lane >> 4) & 3) << 6;
+
+#pragma unroll
+    for (int c = 0; c < R / QC; ++c) {
+#pragma unroll
+        for (int j = 0; j < QC; ++j) {
+            const int wl = wl_lane | (j & 3) << 4 | (j >> 2) << 8;
+            stage[(wl + 16 * (wl >> 6)) * P2 + wave] = v[c * QC + j];
+        }
+        lds_barrier();
+        for (int cc = threadIdx.x / TPC; cc < COLS; cc += CPP) {
+            const float *src = stage + (cc + 16 * (cc >> 6)) * P2 + my_rows;
+            float vals[PACK];
+#pragma unroll
+            for (int r = 0; r < PACK; ++r) {
+                if constexpr (DT == KERDOCK_FP8E4M3) vals[r] = src[r] / scale[r];
+                else vals[r] = src[r];
+            }
+            const size_t col = (size_t)b * D + (size_t)c * COLS + cc;
+            out32[col * col_words + (size_t)(i0 + my_rows) / PACK] = S::pack(vals);
+        }
+        lds_barrier();
+    }
+}
+
 // --------------------------------------------------------- identity block --
 // T[(d/2) d + w][i] = sqrt(d) A[i][w] for w < n, 0 for n <= w < d: a scaled
 // transpose through a 64 x 64 LDS tile.
@@ -308,6 +474,13 @@ __global__ void k_read_columns(const void *__restrict__ table, int m, int pitch,
 
 // -------------------------------------------------------------- launchers --
 
+// table build kernel: 2 = k_table_build2 (d >= 256), 1 = k_table_build;
+// KERDOCK_BUILD selects one (for measurements), default 2
+static int build_variant() {
+    const char *v = getenv("KERDOCK_BUILD");
+    return (v && *v == '1') ? 1 : 2;
+}
+
 int launch_signs(const uint16_t *masks, int k, uint32_t *signs, hipStream_t s) {
     const int d = 1 << k;
     const int wpb = d >= 32 ? d / 32 : 1, nb = d / 2;
@@ -328,8 +501,18 @@ int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dt
 template <int LOGD, int DT>
 static int build_kd(const float *A, int m, int n, int pitch, const uint32_t *signs,
                     const float *scales, void *table, hipStream_t s) {
-    const int strips = pitch / BuildShape<DT>::ROWS;
     const int nb = (1 << LOGD) / 2;
+    if constexpr (LOGD >= 8) {
+        if (build_variant() == 2) {
+            const int strips = pitch / ROWS2;
+            const int xcd_map = (strips % 8 == 0) ? 1 : 0;
+            hipLaunchKernelGGL((k_table_build2<LOGD, DT>), dim3(strips * nb), dim3(ROWS2 * 64), 0, s, A, m, n, pitch,
+                               signs, scales, table, strips, xcd_map);
+            KD_LAUNCH("k_table_build2");
+            return KERDOCK_OK;
+        }
+    }
+    const int strips = pitch / BuildShape<DT>::ROWS;
     const int xcd_map = (strips % 8 == 0) ? 1 : 0;
     hipLaunchKernelGGL((k_table_build<LOGD, DT>), dim3(strips * nb), dim3(BuildShape<DT>::THREADS), 0, s, A,
                        m, n, pitch, signs, scales, table, strips, xcd_map);

@@ -98,6 +98,8 @@ constexpr long long GATHER_MIN_WGS = 2048;
 GatherShape gather_shape(kerdock_dtype dt, int pitch, long long work = 1ll << 40);
 // draws per FP32 partial sum for a call with J draws per batch
 int chunk_for(const kerdock_handle_s *h, int J, int requested);
+// whether a call with J draws per batch groups its draws by basis
+int use_bucket(const kerdock_handle_s *h, int J);
 
 }  // namespace kd
 
@@ -125,6 +127,7 @@ struct kerdock_handle_s {
     hipEvent_t ev[5] = {};        // kernel timing events (created on first use)
     int tune_chunk = 0;           // draws per gather workgroup (0: default)
     int tune_unroll = 0;          // draws in flight per thread (0: default)
+    int tune_bucket = -1;         // group draws by basis: 1 / 0, -1: the default rule
     kerdock_learned_s *learned = nullptr;   // attached learned-proposal state
     float row_norm2_max = 0.f;    // |A|_{2->inf}^2: largest squared row norm
 };

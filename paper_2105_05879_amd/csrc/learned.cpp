@@ -16,18 +16,18 @@ namespace kd {
 int gemm_bf16(bool ak, bool bk, const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K,
               int epi, const float *bias, const uint16_t *mask, int ldm, float *C32, uint16_t *C16, int ldc,
               hipStream_t s);
-int gemm_f32(bool ak, bool bk, const float *A, int lda, const float *B, int ldb, int M, int N, int K, float *C,
-             int ldc, const float *Xdot, float *rowpart, hipStream_t s);
 int launch_to_bf16(const float *x, uint16_t *y, size_t n, hipStream_t s);
 int launch_colsum(const float *dz, int B, int N, float *db, hipStream_t s);
 int launch_bce(const float *z, const uint8_t *y, size_t n, float pos_w, float *dz, uint16_t *dz16,
                float *terms, float *loss, hipStream_t s);
 int launch_adam(float *w, const float *g, float *m, float *v, uint16_t *w16, size_t n, float lr, float b1,
                 float b2, float eps, int step, hipStream_t s);
-int launch_rowsum(const float *parts, int B, int P, float *E, hipStream_t s);
 int launch_features(int k, const float *X, int B, int n, float *F, uint16_t *F16, hipStream_t s);
 int launch_topc_logits(const float *Z, int B, int m, int c, int32_t *cand, int32_t *ncand, hipStream_t s);
-int launch_fallback_flags(const float *E, const float *vsum2, int B, float tol, int32_t *flags, hipStream_t s);
+int launch_gram2(const float *A, int m, int n, float *Ghi, float *Glo, float *fro2, hipStream_t s);
+int launch_energy_flags(const float *X, int B, int n, int m, int c, const float *Ghi, const float *Glo,
+                        const float *fro2, const float *vsum2, float eps, float *Zp, float *Ze, int32_t *flags,
+                        float *dbg_energy, hipStream_t s);
 int launch_survivors(const SurvArgs &a, int batch, hipStream_t s);
 int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s_max,
                    const kerdock_apply_params *p, int32_t *out_idx, float *out_val, int32_t *out_cnt,
@@ -54,7 +54,7 @@ struct kerdock_mlp_s {
 // the learned state attached to a handle
 struct kerdock_learned_s {
     kerdock_mlp net = nullptr;
-    float *Gram = nullptr;            // [n][n] = A^T A
+    float *Gram = nullptr;            // [2][n][n]: A^T A = Ghi + Glo (compensated), then |A|_F^2
     void *ws = nullptr;
     size_t ws_bytes = 0;
 };
@@ -300,13 +300,13 @@ int kerdock_learned_attach(kerdock_handle h, kerdock_mlp net) {
     kerdock_learned_s *L = h->learned;
     if (!L) {
         L = new kerdock_learned_s();
-        if (hipMalloc((void **)&L->Gram, (size_t)h->n * h->n * 4) != hipSuccess) {
+        const size_t nn = (size_t)h->n * h->n;
+        if (hipMalloc((void **)&L->Gram, (2 * nn + 64) * 4) != hipSuccess) {
             delete L;
             return fail(KERDOCK_ERR_OOM, "Gram matrix");
         }
-        // G = A^T A: Ahat(i, k) = A[k][i], Bhat(j, k) = A[k][j]
-        int rc = gemm_f32(true, true, h->A, h->n, h->A, h->n, h->n, h->n, h->m, L->Gram, h->n, nullptr, nullptr,
-                          nullptr);
+        // G = A^T A as a compensated pair, and |A|_F^2
+        int rc = launch_gram2(h->A, h->m, h->n, L->Gram, L->Gram + nn, L->Gram + 2 * nn, nullptr);
         hipError_t e = hipDeviceSynchronize();
         if (rc != KERDOCK_OK || e != hipSuccess) {
             (void)hipFree(L->Gram);
@@ -335,10 +335,9 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
     kerdock_mlp_s *n = L->net;
     int rc = ensure_act(n, B);
     if (rc != KERDOCK_OK) return rc;
-    // workspace: candidates, counts, verified energies, energy parts, energies
-    const int parts = (h->n + 63) / 64;
-    const size_t oc = 0, onc = al((size_t)B * s_max * 4), ov = onc + al((size_t)B * 4), op = ov + al((size_t)B * 4),
-                 oe = op + al((size_t)B * parts * 4), total = oe + al((size_t)B * 4);
+    // workspace: candidates, counts, verified energies, G x as pairs
+    const size_t oc = 0, onc = al((size_t)B * s_max * 4), ov = onc + al((size_t)B * 4), oz = ov + al((size_t)B * 4),
+                 total = oz + 2 * al((size_t)B * h->n * 4);
     if (total > L->ws_bytes) {
         (void)hipDeviceSynchronize();
         (void)hipFree(L->ws);
@@ -351,8 +350,8 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
     int32_t *cand = reinterpret_cast<int32_t *>(w + oc);
     int32_t *ncand = reinterpret_cast<int32_t *>(w + onc);
     float *vs2 = reinterpret_cast<float *>(w + ov);
-    float *rowpart = reinterpret_cast<float *>(w + op);
-    float *E = reinterpret_cast<float *>(w + oe);
+    float *Zp = reinterpret_cast<float *>(w + oz);
+    float *Ze = reinterpret_cast<float *>(w + oz + al((size_t)B * h->n * 4));
 
     // L1 features, L2 MLP, L3 top-s_max logits, L4 exact dots + threshold
     rc = launch_features(h->k, X, B, h->n, nullptr, n->F16, s);
@@ -361,11 +360,12 @@ int kerdock_learned_apply(kerdock_handle h, const float *X, int B, float eps, in
     SurvArgs va{h->A, h->n, X, cand, ncand, s_max, eps, out_idx, out_val, out_cnt, nullptr, nullptr, vs2,
                 nullptr, surv_vec4(X, h->n)};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, B, s);
-    // L5 energy check: |Ax|^2 = x^T G x against the verified energy
+    // L5 certified energy check: |Ax|^2 = x^T G x against the verified energy
+    const size_t nn = (size_t)h->n * h->n;
+    float *dbg_energy = (p->dbg_mu && h->m >= 3) ? p->dbg_mu : nullptr;
     if (rc == KERDOCK_OK)
-        rc = gemm_f32(false, false, X, h->n, L->Gram, h->n, B, h->n, h->n, nullptr, h->n, X, rowpart, s);
-    if (rc == KERDOCK_OK) rc = launch_rowsum(rowpart, B, parts, E, s);
-    if (rc == KERDOCK_OK) rc = launch_fallback_flags(E, vs2, B, 0.5f * eps * eps, fallback, s);
+        rc = launch_energy_flags(X, B, h->n, h->m, s_max, L->Gram, L->Gram + nn, L->Gram + 2 * nn, vs2, eps, Zp, Ze,
+                                 fallback, dbg_energy, s);
     // debug: the candidate set C of every row (ascending, padded with -1)
     if (rc == KERDOCK_OK && p->dbg_survivors) {
         hipError_t e = hipMemcpyAsync(p->dbg_survivors, cand, (size_t)B * s_max * 4, hipMemcpyDeviceToDevice, s);

@@ -7,8 +7,8 @@
 //               and activations as GEMM inputs and FP32 accumulation (MFMA
 //               16x16x16 BF16); FP32 master weights, Adam;
 //   loss        binary cross-entropy with logits, positive weight w+:
-//               mean over all entries of -[w+ y log s(z) + (1-y) log(1-s(z))];
-//   energy      E = x^T G x = |Ax|^2 with G = A^T A (FP32 MFMA 16x16x4).
+//               mean over all entries of -[w+ y log s(z) + (1-y) log(1-s(z))].
+// (The energy check of the learned apply is in energy.hip.)
 //
 // GEMM convention: C[M x N] = Ahat Bhat^T with Ahat M x K and Bhat N x K.  An
 // operand is either "row" (element (i, k) at P[i ld + k]) or "k-major"
@@ -127,111 +127,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
             }
 }
 
-// ------------------------------------------------------------ FP32 GEMM --
-// K tile 16; MFMA 16x16x4 FP32: lane l holds row (column) l % 16, k = l / 16.
-template <bool AK, bool BK>
-__global__ __launch_bounds__(256) void k_gemm_f32(const float *__restrict__ A, int lda,
-                                                  const float *__restrict__ B, int ldb, int M, int N, int K,
-                                                  float *__restrict__ C, int ldc,
-                                                  const float *__restrict__ Xdot, float *__restrict__ rowpart) {
-    constexpr int KT = 16, KP = KT + 1;
-    __shared__ float As[GT][KP];
-    __shared__ float Bs[GT][KP];
-    __shared__ float rs[GT][2];
-    const int i0 = blockIdx.y * GT, j0 = blockIdx.x * GT;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
-    f32x4 acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += KT) {
-        // 64 x 16 = 1024 elements, 4 per thread
-        if (!AK) {
-            const int r = tid >> 2, seg = (tid & 3) * 4, i = i0 + r;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = k0 + seg + e;
-                As[r][seg + e] = (i < M && k < K) ? A[(size_t)i * lda + k] : 0.f;
-            }
-        } else {
-            const int kr = tid >> 4, seg = (tid & 15) * 4, k = k0 + kr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int i = i0 + seg + e;
-                As[seg + e][kr] = (i < M && k < K) ? A[(size_t)k * lda + i] : 0.f;
-            }
-        }
-        if (!BK) {
-            const int r = tid >> 2, seg = (tid & 3) * 4, j = j0 + r;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int k = k0 + seg + e;
-                Bs[r][seg + e] = (j < N && k < K) ? B[(size_t)j * ldb + k] : 0.f;
-            }
-        } else {
-            const int kr = tid >> 4, seg = (tid & 15) * 4, k = k0 + kr;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = j0 + seg + e;
-                Bs[seg + e][kr] = (j < N && k < K) ? B[(size_t)k * ldb + j] : 0.f;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KT; kk += 4) {
-            float fa[2], fb[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) fa[a] = As[wi + a * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) fb[b] = Bs[wj + b * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-    if (C) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = i0 + wi + a * 16 + 4 * (lane >> 4) + v;
-                    const int j = j0 + wj + b * 16 + (lane & 15);
-                    if (i < M && j < N) C[(size_t)i * ldc + j] = acc[a][b][v];
-                }
-    }
-    if (Xdot) {
-        // rowpart[i][blockIdx.x] = sum_{j in tile} C[i][j] Xdot[i][j] (ldc = row pitch of Xdot)
-        if (tid < GT * 2) rs[tid >> 1][tid & 1] = 0.f;
-        __syncthreads();
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int il = wi + a * 16 + 4 * (lane >> 4) + v;
-                const int i = i0 + il;
-                float s = 0.f;
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int j = j0 + wj + b * 16 + (lane & 15);
-                    if (i < M && j < N) s += acc[a][b][v] * Xdot[(size_t)i * ldc + j];
-                }
-                // reduce over the 16 lanes that share this row
-#pragma unroll
-                for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                if ((lane & 15) == 0) rs[il][wave & 1] = s;
-            }
-        __syncthreads();
-        if (tid < GT && i0 + tid < M) rowpart[(size_t)(i0 + tid) * gridDim.x + blockIdx.x] = rs[tid][0] + rs[tid][1];
-    }
-}
-
 // ---------------------------------------------------------- small kernels --
 __global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -295,15 +190,6 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
         w[i] = wi;
         if (w16) w16[i] = bf16_rne(wi);
     }
-}
-
-// E[i] = sum of the per-tile parts of row i (fixed order)
-__global__ void k_rowsum(const float *__restrict__ parts, int B, int P, float *__restrict__ E) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= B) return;
-    float s = 0.f;
-    for (int p = 0; p < P; ++p) s += parts[(size_t)i * P + p];
-    E[i] = s;
 }
 
 // f = H x / sqrt(d): one wave per vector, element x = q*64 + lane in
@@ -375,17 +261,6 @@ int gemm_bf16(bool ak, bool bk, const uint16_t *A, int lda, const uint16_t *B, i
     return KERDOCK_OK;
 }
 
-int gemm_f32(bool ak, bool bk, const float *A, int lda, const float *B, int ldb, int M, int N, int K, float *C,
-             int ldc, const float *Xdot, float *rowpart, hipStream_t s) {
-    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-    if (!ak && !bk) hipLaunchKernelGGL((k_gemm_f32<false, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Xdot, rowpart);
-    else if (!ak && bk) hipLaunchKernelGGL((k_gemm_f32<false, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Xdot, rowpart);
-    else if (ak && !bk) hipLaunchKernelGGL((k_gemm_f32<true, false>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Xdot, rowpart);
-    else hipLaunchKernelGGL((k_gemm_f32<true, true>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K, C, ldc, Xdot, rowpart);
-    KD_LAUNCH("k_gemm_f32");
-    return KERDOCK_OK;
-}
-
 static dim3 grid1d(size_t n) {
     size_t b = (n + 255) / 256;
     return dim3((unsigned)(b < 8192 ? (b ? b : 1) : 8192));
@@ -416,12 +291,6 @@ int launch_adam(float *w, const float *g, float *m, float *v, uint16_t *w16, siz
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
     hipLaunchKernelGGL(k_adam, grid1d(n), dim3(256), 0, s, w, g, m, v, w16, n, lr, b1, b2, eps, c1, c2);
     KD_LAUNCH("k_adam");
-    return KERDOCK_OK;
-}
-
-int launch_rowsum(const float *parts, int B, int P, float *E, hipStream_t s) {
-    hipLaunchKernelGGL(k_rowsum, dim3((B + 255) / 256), dim3(256), 0, s, parts, B, P, E);
-    KD_LAUNCH("k_rowsum");
     return KERDOCK_OK;
 }
 

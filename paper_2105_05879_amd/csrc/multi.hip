@@ -3,9 +3,11 @@
 // unroll depth.
 //
 // A plan binds, for every handle q, its input rows X_q, its outputs and its
-// streaming parameters.  One run is five launches on one stream:
+// streaming parameters.  One run is six launches on one stream:
 //   k_multi_begin        reset the work counter (a kernel, not a memset, so
 //                        that graph replays reset it too);
+//   k_multi_sort         the draws of every (handle, vector, batch) of the
+//                        handles that group them by basis (draw_sort);
 //   k_multi_draw_gather  persistent: every workgroup takes work items
 //                        (handle, vector, chunk, segment) from the counter,
 //                        longest columns first, and runs the same draws +
@@ -40,6 +42,13 @@ struct MultiSurv {
     const SurvArgs *surv;            // device [nh]
 };
 
+struct MultiSort {
+    int nh;
+    int offset[MAX_MULTI + 1];       // prefix sums of batch K
+    int K[MAX_MULTI];
+    const DGArgs *dg;                // device [nh]
+};
+
 // item: handle q (4 bits) | segment (4 bits) | chunk id (24 bits) | vector t (32 bits)
 __device__ __forceinline__ void unpack_item(uint64_t v, int &q, int &seg, int &cid, int &t) {
     q = (int)(v >> 60);
@@ -61,10 +70,9 @@ template <int DT, int TILES, int UNROLL, int P>
 __global__ __launch_bounds__(GATHER_THREADS) void k_multi_draw_gather(
     const DGArgs *__restrict__ hd, const int *__restrict__ nchunks, const int *__restrict__ grouped,
     const uint64_t *__restrict__ items, int nitems, int *counter) {
-    constexpr int E = Elems<DT>::N;
-    __shared__ uint32_t s_ell[MAX_CHUNK];
-    __shared__ float s_coef[MAX_CHUNK];
-    __shared__ float red[GATHER_THREADS * E];
+    constexpr size_t SMEM = DGSmem<DT, true, P>::BYTES > DGSmem<DT, false, P>::BYTES ? DGSmem<DT, true, P>::BYTES
+                                                                                     : DGSmem<DT, false, P>::BYTES;
+    __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ int s_item;
     for (;;) {
         __syncthreads();                       // the previous item is finished
@@ -76,9 +84,9 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_multi_draw_gather(
         unpack_item(items[it], q, seg, cid, t);
         const DGArgs &a = hd[q];
         if (grouped[q])
-            draw_gather<DT, TILES, UNROLL, true, P>(a, t, cid, seg, nchunks[q], s_ell, s_coef, red);
+            draw_gather<DT, TILES, UNROLL, true, P>(a, t, cid, seg, nchunks[q], smem);
         else
-            draw_gather<DT, TILES, UNROLL, false, P>(a, t, cid, seg, nchunks[q], s_ell, s_coef, red);
+            draw_gather<DT, TILES, UNROLL, false, P>(a, t, cid, seg, nchunks[q], smem);
     }
 }
 
@@ -96,6 +104,16 @@ __global__ __launch_bounds__(SELECT_THREADS) void k_multi_select(MultiSelect ms)
     __shared__ uint32_t sel_state[2];
     const int q = find_handle(ms.offset, ms.nh, blockIdx.x);
     select_vec<KMAX>(ms.sel[q], blockIdx.x - ms.offset[q], key, hist, scan_sh, sel_state);
+}
+
+// one workgroup per (handle, vector, batch)
+__global__ __launch_bounds__(SORT_THREADS) void k_multi_sort(MultiSort ms) {
+    extern __shared__ uint32_t cur[];
+    __shared__ int sh[SORT_THREADS / 64 + 1];
+    const int q = find_handle(ms.offset, ms.nh, blockIdx.x);
+    const int r = blockIdx.x - ms.offset[q];
+    if (!ms.dg[q].bucket) return;              // this handle draws inside the gather
+    draw_sort(ms.dg[q], r / ms.K[q], r % ms.K[q], cur, sh);
 }
 
 __global__ __launch_bounds__(SURV_THREADS) void k_multi_survivors(MultiSurv mv) {
@@ -117,6 +135,9 @@ struct kerdock_multi_s {
     int nitems = 0, total_batch = 0, max_m = 1, max_smax = 1, grid = 0;
     kd::MultiSelect msel{};
     kd::MultiSurv msurv{};
+    kd::MultiSort msort{};
+    int sort_wgs = 0;
+    size_t sort_lds = 0;
     void *ws = nullptr;               // device: everything below
     kd::DGArgs *dg_dev = nullptr;
     kd::SelArgs *sel_dev = nullptr;
@@ -134,6 +155,7 @@ namespace kd {
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 int gather_chunk_max();
+size_t sort_lds_bytes(int k);
 
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -212,6 +234,7 @@ static int resident(const kerdock_multi_s *pl, int cus) {
 
 static int multi_enqueue(kerdock_multi_s *pl, hipStream_t s) {
     hipLaunchKernelGGL(k_multi_begin, dim3(1), dim3(64), 0, s, pl->counter);
+    hipLaunchKernelGGL(k_multi_sort, dim3(pl->sort_wgs), dim3(SORT_THREADS), pl->sort_lds, s, pl->msort);
     multi_gather(pl, s);
     const size_t key_bytes = (size_t)pl->max_m * 4;
     dim3 g(pl->total_batch), b(SELECT_THREADS);
@@ -273,8 +296,8 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
     std::vector<DGArgs> dg(nh);
     std::vector<SelArgs> sel(nh);
     std::vector<SurvArgs> sv(nh);
-    std::vector<int> nchunks(nh), grouped(nh), chunk(nh), cpb(nh);
-    std::vector<size_t> off_partial(nh), off_surv(nh), off_nsurv(nh);
+    std::vector<int> nchunks(nh), grouped(nh), chunk(nh), cpb(nh), bucket(nh);
+    std::vector<size_t> off_partial(nh), off_jlist(nh), off_sorted(nh), off_surv(nh), off_nsurv(nh);
     size_t off = 0;
     const size_t off_dg = off; off += al(sizeof(DGArgs) * nh);
     const size_t off_sel = off; off += al(sizeof(SelArgs) * nh);
@@ -314,6 +337,13 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         pl->s_max[q] = s_max[q];
         pl->m[q] = h->m;
         off_partial[q] = off; off += al((size_t)batch[q] * nchunks[q] * h->pitch * 4);
+        bucket[q] = use_bucket(h, J);
+        off_jlist[q] = off; off += bucket[q] ? al((size_t)batch[q] * J * K * 4) : 0;
+        off_sorted[q] = off; off += bucket[q] ? al((size_t)batch[q] * J * K * 4) : 0;
+        pl->msort.offset[q] = pl->sort_wgs;
+        pl->msort.K[q] = K;
+        pl->sort_wgs += batch[q] * K;
+        pl->sort_lds = std::max(pl->sort_lds, sort_lds_bytes(h->k));
         off_surv[q] = off; off += al((size_t)batch[q] * s_max[q] * 4);
         off_nsurv[q] = off; off += al((size_t)batch[q] * 4);
         items += (size_t)batch[q] * nchunks[q];
@@ -321,6 +351,8 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         pl->total_batch += batch[q];
     }
     pl->msel.offset[nh] = pl->total_batch;
+    pl->msort.offset[nh] = pl->sort_wgs;
+    pl->msort.nh = nh;
     const size_t off_items = off; off += al(sizeof(uint64_t) * items);
     if (items > (size_t)0x7FFFFFFF) { delete pl; return fail(KERDOCK_ERR_INVALID_ARG, "multi: too many work items"); }
     if (hipMalloc(&pl->ws, off) != hipSuccess) { delete pl; return fail(KERDOCK_ERR_OOM, "multi workspace"); }
@@ -361,6 +393,10 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         a.tpc = gs.tpc;
         a.pitch = h->pitch;
         a.partial = reinterpret_cast<float *>(ws + off_partial[q]);
+        a.bucket = bucket[q];
+        a.jlist = bucket[q] ? reinterpret_cast<uint32_t *>(ws + off_jlist[q]) : nullptr;
+        a.sorted = bucket[q] ? reinterpret_cast<uint32_t *>(ws + off_sorted[q]) : nullptr;
+        a.perm = nullptr;
         a.dbg_samples = nullptr;
         a.dbg_coef = nullptr;
         int32_t *sv_ = reinterpret_cast<int32_t *>(ws + off_surv[q]);
@@ -398,6 +434,7 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
     pl->msurv.nh = nh;
     for (int q = 0; q <= nh; ++q) pl->msurv.offset[q] = pl->msel.offset[q];
     pl->msurv.surv = pl->surv_dev;
+    pl->msort.dg = pl->dg_dev;
     int tuned = 0;
     for (int q = 0; q < nh; ++q) tuned = std::max(tuned, hs[q]->tune_unroll);
     pl->unroll = tuned > 0 ? tuned : 8;
@@ -463,6 +500,9 @@ int kerdock_multi_autotune(kerdock_multi plan, void *stream, int *best_unroll) {
     if ((e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) return hip_fail(e, "events");
     float best = 1e30f;
     int best_u = plan->unroll;
+    // the draws of the current stream positions, grouped by basis (they do
+    // not depend on the gather shape that is being timed)
+    hipLaunchKernelGGL(k_multi_sort, dim3(plan->sort_wgs), dim3(SORT_THREADS), plan->sort_lds, s, plan->msort);
     for (int i = 0; i < nc; ++i) {
         plan->unroll = cands[i];
         plan->grid = resident(plan, prop.multiProcessorCount);
@@ -474,7 +514,7 @@ int kerdock_multi_autotune(kerdock_multi plan, void *stream, int *best_unroll) {
             (void)hipEventRecord(b, s);
             if ((e = hipEventSynchronize(b)) != hipSuccess) { (void)hipEventDestroy(a); (void)hipEventDestroy(b); return hip_fail(e, "autotune run"); }
             float ms = 0.f;
-            hipEventElapsedTime(&ms, a, b);
+            (void)hipEventElapsedTime(&ms, a, b);
             tmin = std::min(tmin, ms);
         }
         if (tmin < best) { best = tmin; best_u = cands[i]; }

@@ -56,9 +56,11 @@ def assert_same(a, b):
         assert torch.equal(v1, v2)
 
 
+@pytest.mark.parametrize("bucket", ["0", "1"])
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
-def test_multi_equals_single(orc, dtype):
+def test_multi_equals_single(orc, monkeypatch, dtype, bucket):
     kd = need_gpu()
+    monkeypatch.setenv("KERDOCK_BUCKET", bucket)
     hs, Xs = setup(kd, dtype, SHAPES)
     ref = single_outputs(kd, hs, Xs)
     got = kd.kerdock_sparse_apply_multi(hs, Xs, PARAMS, EPS, S_MAX)

@@ -5,6 +5,7 @@ with the same bfloat16 rounding points; the learned apply against the exact
 definition (verified values, the fallback guarantee) and against the plain
 path (fallback rows equal kerdock_sparse_apply bit for bit); and a small
 training run that shows what the network gains over the plain method."""
+import ctypes
 import math
 
 import numpy as np
@@ -216,6 +217,109 @@ def test_learned_apply_exact_and_fallback(orc):
             assert np.all(np.abs(val[t][:c] - Y[t][idx[t][:c]]) <= 1e-5 * np.abs(Y[t][idx[t][:c]]) + 1e-9)
             assert set(np.nonzero(np.abs(Y[t]) >= eps * (1 + 1e-6))[0]) <= set(idx[t][:c])
             assert np.all(np.abs(val[t][:c]) >= eps)
+    h.destroy()
+    net.destroy()
+
+
+def test_energy_check_is_sound_with_dense_gram(orc):
+    """The fallback guarantee in floating point, on a dense, ill-conditioned
+    Gram matrix: A = diag(d) Q with Q Haar-orthogonal and d log-uniform in
+    [0.1, 10] (|A|_2 = 10), and a proposer whose candidate set C is fixed and
+    never holds row R (logits = biases, R's far below).  Groups of x:
+      1. unit x with |(Ax)_R| = 1.5 eps, support of the rest in C -> must
+         fall back;
+      2. as 1, the rest on the rows of largest d (|Ax|^2 up to ~100);
+      3. unit x with Ax supported in C                       -> certified,
+         accepted;
+      4. 300 times a group-3 vector (not unit: the rounding bound on
+         |Ax|^2 exceeds eps^2 / 2)                            -> falls back.
+    Accepted rows are exact, and the computed |Ax|^2 and verified energy
+    lie within the reported bound of their FP64 values."""
+    kd = need_gpu()
+    n, s_max, eps, R = 512, 40, 0.05, 5
+    rng = np.random.default_rng(77)
+    d = np.exp(rng.uniform(np.log(0.1), np.log(10.0), n))
+    d[0] = 10.0
+    A = (d[:, None] * workloads.haar_orthogonal(n, rng)).astype(np.float32)
+    A64 = A.astype(np.float64)
+    G64 = A64.T @ A64
+    assert np.count_nonzero(np.abs(G64 - np.diag(np.diag(G64))) > 1e-3) > n * n // 2     # dense Gram
+    bias = -np.arange(n, dtype=np.float64)
+    bias[R] = -1e4
+    C = set(np.argsort(-bias, kind="stable")[:s_max].tolist())
+    assert R not in C
+    inside = np.array(sorted(C))
+    big = inside[np.argsort(-d[inside], kind="stable")[:6]]
+    xr = np.linalg.solve(A64, np.eye(n)[R])
+
+    def unit_x(y_rest, r_val):
+        # x = A^-1 (y_rest + c e_R) / norm with (Ax)_R = r_val: c = r_val |x0 + c xr| (a contraction)
+        x0 = np.linalg.solve(A64, y_rest)
+        c = 0.0
+        for _ in range(60):
+            c = r_val * np.linalg.norm(x0 + c * xr)
+        x = x0 + c * xr
+        return x / np.linalg.norm(x)
+
+    X = []
+    for g in range(4):
+        for _ in range(12):
+            y = np.zeros(n)
+            sup = big if g == 1 else rng.choice(inside, size=6, replace=False)
+            y[sup] = rng.standard_normal(6)
+            x = unit_x(y, 1.5 * eps * rng.choice([-1.0, 1.0]) if g < 2 else 0.0)
+            X.append(300.0 * x if g == 3 else x)
+    X = np.stack(X).astype(np.float32)
+    X64 = X.astype(np.float64)
+    Ax = X64 @ A64.T
+    assert np.all(np.abs(Ax[:24, R]) >= eps)
+    h = kd.kerdock_prepare(torch.from_numpy(A).cuda(), "bf16")
+    dims = (h.info.d, 32, 32, n)
+    net = kd.kerdock_mlp_create(*dims, seed=1)
+    P = rand_params(dims, 2)
+    o3 = dims[1] * dims[0] + dims[1] + dims[2] * dims[1] + dims[2]
+    P[o3:o3 + n * dims[2]] = 0.0                  # W3 = 0: logits = b3
+    P[o3 + n * dims[2]:] = bias.astype(np.float32)
+    kd.kerdock_mlp_set_params(net, P)
+    kd.kerdock_learned_attach(h, net)
+    Xt = torch.from_numpy(X).cuda()
+    B = X.shape[0]
+    out = tuple(torch.empty(sh, dtype=dt, device="cuda") for sh, dt in
+                (((B, s_max), torch.int32), ((B, s_max), torch.float32), ((B,), torch.int32)))
+    fb = torch.empty((B,), dtype=torch.int32, device="cuda")
+    cand = torch.empty((B, s_max), dtype=torch.int32, device="cuda")
+    energy = torch.zeros((B, n), dtype=torch.float32, device="cuda")
+    p = kd.ApplyParams(J=2000, K=1, seed=3, t0=0, tau=0.0, chunk=0)
+    p.dbg_survivors = cand.data_ptr()
+    p.dbg_mu = energy.data_ptr()
+    kd._check(kd.lib().kerdock_learned_apply(h.ptr, kd._dev(Xt, torch.float32, "X"), B, eps, s_max,
+                                             ctypes.byref(p), kd._ptr(out[0]), kd._ptr(out[1]), kd._ptr(out[2]),
+                                             kd._ptr(fb), kd._stream(None)))
+    torch.cuda.synchronize()
+    cand, fb = cand.cpu().numpy(), fb.cpu().numpy()
+    idx, val, cnt = (o.cpu().numpy() for o in out)
+    en = energy.cpu().numpy()[:, :3].astype(np.float64)
+    for t in range(B):
+        assert set(cand[t].tolist()) == C
+        E64 = float(Ax[t] @ Ax[t])
+        S64 = float(sum(Ax[t][i] ** 2 for i in C))
+        E, S, bound = en[t]
+        assert abs(E - E64) <= bound and abs(S - S64) <= bound, (t, E, E64, S, S64, bound)
+        missing = any(abs(Ax[t][i]) >= eps for i in range(n) if i not in C)
+        g = t // 12
+        if missing:
+            assert fb[t] == 1, t
+        if g in (0, 1):
+            assert missing and fb[t] == 1
+        elif g == 2:
+            assert fb[t] == 0 and bound < eps * eps / 2, (t, bound)
+        else:
+            assert fb[t] == 1 and bound >= eps * eps / 2, (t, bound)
+        if fb[t] == 0:
+            c = cnt[t]
+            want = [i for i in sorted(C) if abs(Ax[t][i]) >= eps]
+            assert idx[t][:c].tolist() == want
+            assert np.all(np.abs(val[t][:c] - Ax[t][idx[t][:c]]) <= 1e-5 * np.abs(Ax[t][idx[t][:c]]))
     h.destroy()
     net.destroy()
 

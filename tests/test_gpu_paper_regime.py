@@ -92,3 +92,33 @@ def test_exact_recovery_shared_draws(orc, regime, dtype):
     assert len(bad) <= MAX_FAIL
     for t in bad:
         confirm_with_oracle(orc, w, t, dtype, 2021, t // kd.SHARED_TILE, 1)
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_toy_model_against_oracle(orc, shared):
+    """Section 2.1's toy model (the regime sweep's workload): n = 4096, A
+    orthogonal, each entry of Ax N(0, 1) with probability p = 5 / n, unit x,
+    eps = alpha / sqrt(p n) with alpha = 0.5, s_max = 10 p n = 50, K = 2, BF16
+    table; the per-vector and the shared-draw forms against the oracle's run
+    of the same draws."""
+    from gpu_common import shared_terms
+    from test_gpu_parity import check_case
+    kd = need_gpu()
+    n, pn, J2, K2 = 4096, 5, 128, 2
+    p = pn / n
+    w = workloads.toy_model(3, p, n=n)
+    eps = 0.5 / np.sqrt(pn)
+    s_max = 10 * pn
+    h = kd.kerdock_prepare(torch.from_numpy(w.A).cuda(), "bf16")
+    fn = kd.kerdock_sparse_apply_shared if shared else kd.kerdock_sparse_apply
+    idx, val, cnt, dbg = fn(h, torch.from_numpy(w.X).cuda(), eps, s_max, J2, K2, 99, t0=0, debug=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in dbg.items()}
+    g.update(idx=idx.cpu().numpy(), val=val.cpu().numpy(), cnt=cnt.cpu().numpy())
+    info = h.info
+    h.destroy()
+    A64, X64 = w.A.astype(np.float64), w.X.astype(np.float64)
+    r = orc.sparse_apply(A64, X64, J2, K2, eps, s_max, seed=99, t0=0, table_mode="bf16", debug=True,
+                         tile=kd.SHARED_TILE if shared else 0)
+    kw = dict(chunk=J2, terms=shared_terms(J2, "bf16")) if shared else {}
+    assert check_case(orc, A64, X64, g, r, info, eps, J2, K2, s_max, "bf16", **kw) <= 1

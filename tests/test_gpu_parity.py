@@ -113,13 +113,15 @@ APPLY_CASES = [
 ]
 
 
-def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, eps=None, chunk=0):
-    if m == n and n >= 64:
-        A = workloads.structured_dictionary(n, np.random.default_rng(n)).astype(np.float32)
-    else:
-        A = rand_A(m, n, m * 31 + n)
+def run_case(orc, kd, m, n, J, K, s_max, dtype, B=3, seed=3001, t0=5, tau=0.0, eps=None, chunk=0, A=None, X=None):
+    if A is None:
+        if m == n and n >= 64:
+            A = workloads.structured_dictionary(n, np.random.default_rng(n)).astype(np.float32)
+        else:
+            A = rand_A(m, n, m * 31 + n)
     A64 = A.astype(np.float64)
-    X = unit_rows(B, n, m + 3 * n)
+    if X is None:
+        X = unit_rows(B, n, m + 3 * n)
     X64 = X.astype(np.float64)
     if eps is None:
         eps = float(np.quantile(np.abs(X64 @ A64.T), 0.9)) + 1e-6
@@ -184,13 +186,59 @@ def check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype, tau=0.0, chun
     return exceptions
 
 
+@pytest.mark.parametrize("bucket", ["0", "1"])
 @pytest.mark.parametrize("m,n,J,K,s_max", APPLY_CASES)
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_apply_parity(orc, m, n, J, K, s_max, dtype):
+def test_apply_parity(orc, monkeypatch, m, n, J, K, s_max, dtype, bucket):
+    """Both orders of the draws: as drawn (bucket 0) and grouped by basis
+    with the per-basis transform of the coefficients (bucket 1)."""
     kd = need_gpu()
+    monkeypatch.setenv("KERDOCK_BUCKET", bucket)
     A64, X64, g, r, info, eps = run_case(orc, kd, m, n, J, K, s_max, dtype)
     exc = check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype)
     assert exc <= 1
+
+
+# long runs of draws per basis (J several times d/2 + 1), where grouping the
+# draws by basis and transforming each basis once pays; the last case has
+# n > 2048 (two sign words per lane)
+BUCKET_CASES = [
+    (64, 64, 300, 2, 10),
+    (256, 256, 2000, 2, 30),
+    (300, 100, 1500, 3, 40),
+    (70, 300, 2100, 2, 70),
+    (40, 3000, 9000, 1, 20),
+]
+
+
+@pytest.mark.parametrize("bucket", ["0", "1"])
+@pytest.mark.parametrize("m,n,J,K,s_max", BUCKET_CASES)
+@pytest.mark.parametrize("dtype", ["f32", "fp8"])
+def test_apply_parity_long_runs(orc, monkeypatch, m, n, J, K, s_max, dtype, bucket):
+    kd = need_gpu()
+    monkeypatch.setenv("KERDOCK_BUCKET", bucket)
+    A64, X64, g, r, info, eps = run_case(orc, kd, m, n, J, K, s_max, dtype, B=2)
+    assert check_case(orc, A64, X64, g, r, info, eps, J, K, s_max, dtype) <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_plain_workload_parity(orc, dtype):
+    """The plain-method workload: n = 1024, A with i.i.d. N(0, 1/n) entries
+    (general, not orthogonal), x = A^-1 y normalised with y 16-sparse, eps
+    = 0.05, s_max = 10 s = 160; four of its vectors against the oracle."""
+    kd = need_gpu()
+    w = workloads.plain(batch=4)
+    A64, X64, g, r, info, eps = run_case(orc, kd, 1024, 1024, 300, 3, 160, dtype, eps=w.eps, A=w.A, X=w.X)
+    assert check_case(orc, A64, X64, g, r, info, eps, 300, 3, 160, dtype) <= 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "fp8"])
+def test_tall_matrix_at_the_row_cap(orc, dtype):
+    """m = 16384 rows, the largest m that kerdock_prepare accepts: the
+    selection stages one key per row (64 KiB) in LDS."""
+    kd = need_gpu()
+    A64, X64, g, r, info, eps = run_case(orc, kd, 16384, 64, 40, 2, 100, dtype, B=2)
+    assert check_case(orc, A64, X64, g, r, info, eps, 40, 2, 100, dtype) <= 1
 
 
 def test_apply_tau_and_take_all(orc):
@@ -216,12 +264,14 @@ def test_chunk_parameter(orc, chunk):
     check_case(orc, A64, X64, g, r, info, eps, 300, 3, 20, "f32", chunk=chunk)
 
 
+@pytest.mark.parametrize("bucket", ["0", "1"])
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_results_do_not_depend_on_batch_size(orc, dtype):
+def test_results_do_not_depend_on_batch_size(orc, monkeypatch, dtype, bucket):
     """Launch shapes change with the batch (single-tile gather workgroups and
     the split survivor step below 2048 vectors); the outputs of a vector
     depend only on its stream position."""
     kd = need_gpu()
+    monkeypatch.setenv("KERDOCK_BUCKET", bucket)
     n = 1200                                   # 4800-byte FP32 columns: two tiles
     A = rand_A(n, n, 21)
     X = torch.from_numpy(unit_rows(2100, n, 22)).cuda()
