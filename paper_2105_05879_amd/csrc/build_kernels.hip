@@ -80,6 +80,10 @@ __global__ void k_row_scales(const float *__restrict__ A, int m, int n, int pitc
 
 // --------------------------------------------------------- element stores --
 
+// Values already divided by the row scale; gfx950 converts in hardware with
+// round-to-nearest-even: BF16 by v_cvt_pk_bf16_f32, OCP E4M3 by
+// v_cvt_pk_fp8_f32 after a clamp to +-448 (the largest finite E4M3 value:
+// saturation, as the FP8 row scales bound every entry up to rounding).
 template <int DT> struct Store;
 template <> struct Store<KERDOCK_F32> {
     static constexpr int ROWS = 1;   // rows packed per 32-bit store
@@ -88,14 +92,19 @@ template <> struct Store<KERDOCK_F32> {
 template <> struct Store<KERDOCK_BF16> {
     static constexpr int ROWS = 2;
     __device__ static uint32_t pack(const float *v) {
-        return (uint32_t)f32_to_bf16_rne(v[0]) | ((uint32_t)f32_to_bf16_rne(v[1]) << 16);
+        const __bf16 a = (__bf16)v[0], b = (__bf16)v[1];
+        return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
     }
 };
 template <> struct Store<KERDOCK_FP8E4M3> {
     static constexpr int ROWS = 4;
     __device__ static uint32_t pack(const float *v) {
-        return (uint32_t)f32_to_e4m3_sat(v[0]) | ((uint32_t)f32_to_e4m3_sat(v[1]) << 8) |
-               ((uint32_t)f32_to_e4m3_sat(v[2]) << 16) | ((uint32_t)f32_to_e4m3_sat(v[3]) << 24);
+        float c[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = fminf(fmaxf(v[r], -448.0f), 448.0f);
+        int w = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+        w = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], w, true);
+        return (uint32_t)w;
     }
 };
 
@@ -215,10 +224,10 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
     constexpr int ROWS = S::ROWS;
     constexpr int THREADS_PER_COL = BUILD_ROWS / ROWS;
     constexpr int COLS_PER_PASS = BUILD_THREADS / THREADS_PER_COL;
-    float scale[ROWS];
+    float inv_scale[ROWS];
     const int my_rows = (threadIdx.x % THREADS_PER_COL) * ROWS;
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) scale[r] = scales[i0 + my_rows + r];
+    for (int r = 0; r < ROWS; ++r) inv_scale[r] = 1.0f / scales[i0 + my_rows + r];
 
     uint32_t *out32 = reinterpret_cast<uint32_t *>(table);
     const size_t col_words = (size_t)pitch * (DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1) / 4;
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
 #pragma unroll
             for (int r = 0; r < ROWS; ++r) {
                 // FP32 and BF16 tables have unit scales: no division
-                if constexpr (DT == KERDOCK_FP8E4M3) vals[r] = stage[cc * STAGE_PITCH + my_rows + r] / scale[r];
+                if constexpr (DT == KERDOCK_FP8E4M3) vals[r] = stage[cc * STAGE_PITCH + my_rows + r] * inv_scale[r];
                 else vals[r] = stage[cc * STAGE_PITCH + my_rows + r];
             }
             const size_t col = (size_t)b * D + c0 + cc;
@@ -250,29 +259,32 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
 }
 
 // ------------------------------------------------- table build, d >= 256 --
-// The same transform without LDS traffic in the butterflies, in workgroups of
-// ROWS2 waves (two workgroups per CU, so that one's loads and stores overlap
-// the other's arithmetic).  Wave r holds row i0 + r, lane l and register q
-// holding the input element x = q 64 + (l ^ 15):
-//   * register bits (x bits 6..k-1): butterflies inside each lane;
-//   * lane bits 0..3 (xor 1, 2, 4, 8): the partner value arrives by DPP
-//     (quad_perm, row_half_mirror + quad_perm, row_ror:8) and every lane
-//     computes v + s p with s = -1 in the upper lane of the pair, i.e. the
-//     upper lanes hold the negated difference.  Across the four stages this
-//     multiplies output w by (-1)^{w . 15}, which the input order x ^ 15
-//     cancels exactly (H[w][x ^ 15] = (-1)^{w . 15} H[w][x]);
-//   * lane bits 4 and 5: v_permlane16_swap / v_permlane32_swap exchange lane
-//     bit 4 (5) with register bit 0 (1), after which the pair sits in one
-//     lane and the butterfly is local.
+// The same transform with fewer vector instructions, in workgroups of ROWS
+// waves (two or more workgroups per CU, so that one's loads and stores
+// overlap another's arithmetic).  Wave r holds row i0 + r; lane l holds the
+// R = d/64 consecutive input elements x = (l ^ 15) R + q in registers q < R
+// (16-byte loads), r = log2 R, so that
+//   * x bits 0..r-1 (the register index): butterflies inside each lane;
+//   * x bits r..r+3 (lane bits 0..3, xor 1, 2, 4, 8): the partner value
+//     arrives by DPP (quad_perm, row_half_mirror + quad_perm, row_ror:8) and
+//     every lane computes v + s p with s = -1 in the upper lane of the pair,
+//     i.e. the upper lanes hold the negated difference.  Across the four
+//     stages this multiplies output w by (-1)^{w . M} (M = 15 R, the mask of
+//     these bits), which the input order (lane l reads segment l ^ 15)
+//     cancels exactly, H[w][x ^ M] = (-1)^{w . M} H[w][x];
+//   * x bits r+4, r+5 (lane bits 4, 5): v_permlane16_swap / permlane32_swap
+//     exchange lane bit 4 (5) with register bit 0 (1), after which the pair
+//     sits in one lane and the butterfly is local.
 // Output w of register q in lane l:
-//   w = (l & 15) | (q & 1) << 4 | (q >> 1 & 1) << 5 | (l >> 4 & 1) << 6 |
-//       (l >> 5 & 1) << 7 | (q >> 2) << 8.
-// Staging: chunks of up to 1024 columns = register bits 2.. fixed, as [column]
-// [row] with a row pitch of ROWS2 + 1 and 16 empty column slots after every
-// 64 columns (the four 16-lane groups of a write land on distinct banks).
-// The barriers around the staging wait for LDS only: stores to the table
-// need not complete before the next chunk.
-constexpr int ROWS2 = 8;
+//   w = (l >> 4 & 1) | (l >> 5 & 1) << 1 | (q & (R - 4)) | (l & 15) << r |
+//       (q & 3) << (r + 4),
+// so for d = 4096 a chunk of 1024 columns is one value of q & 3.  Staging is
+// [row][slot] with slot = w' ^ ((w' >> 6 & 15) << 2), w' = w mod 1024 (the 64
+// lanes of a write and the 32 columns of a read hit distinct banks), row
+// pitch 1032 floats; each thread then stores 4 consecutive rows of a column
+// (16, 8 or 4 bytes).  The barriers around the staging wait for LDS only:
+// stores to the table need not complete before the next chunk.
+constexpr int STAGE2_PITCH = 1032;
 
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -280,13 +292,16 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// every lane reads a valid lane under these controls, so the old value is
+// never used (undefined: lets the move fold into the consuming instruction)
 template <int CTRL> __device__ __forceinline__ float dpp_f(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
+// the d-point transform of a row held as R = d/64 registers per lane, lane l
+// holding x = (l ^ 15) R + q; output positions as described above
 template <int LOGD> __device__ __forceinline__ void fwht_wave2(float *v) {
-    constexpr int D = 1 << LOGD;
-    constexpr int R = D / 64;
+    constexpr int R = (1 << LOGD) / 64;
     const int lane = threadIdx.x & 63;
     // register bits
 #pragma unroll
@@ -330,21 +345,30 @@ template <int LOGD> __device__ __forceinline__ void fwht_wave2(float *v) {
     }
 }
 
-template <int LOGD, int DT>
-__global__ __launch_bounds__(ROWS2 * 64) void k_table_build2(const float *__restrict__ A, int m, int n, int pitch,
+// PACK consecutive rows of one column in one store of PACK x element bytes
+template <int DT, int PACK> __device__ __forceinline__ void store_rows(unsigned char *dst, const float *vals) {
+    constexpr int SR = Store<DT>::ROWS, NW = PACK / SR;
+    static_assert(PACK % SR == 0 && NW <= 4 && NW != 3, "store of 4, 8 or 16 bytes");
+    uint32_t w[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) w[k] = Store<DT>::pack(vals + k * SR);
+    if constexpr (NW == 1) *reinterpret_cast<uint32_t *>(dst) = w[0];
+    else if constexpr (NW == 2) *reinterpret_cast<uint2 *>(dst) = make_uint2(w[0], w[1]);
+    else *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+template <int LOGD, int DT, int ROWS, int PACK>
+__global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restrict__ A, int m, int n, int pitch,
                                                               const uint32_t *__restrict__ signs,
                                                               const float *__restrict__ scales,
                                                               void *__restrict__ table, int strips, int xcd_map) {
     constexpr int D = 1 << LOGD;
-    constexpr int R = D / 64;
+    constexpr int R = D / 64;                           // elements per lane
     constexpr int WORDS = D / 32;
     constexpr int COLS = D < STAGE_COLS ? D : STAGE_COLS;
     constexpr int QC = COLS / 64;                       // registers per chunk
-    constexpr int P2 = ROWS2 + 1;
-    constexpr int SLOTS = COLS + 16 * (COLS / 64);
-    constexpr int THREADS = ROWS2 * 64;
-    __shared__ float stage[SLOTS * P2];
-    __shared__ uint32_t sbits[WORDS];
+    constexpr int THREADS = ROWS * 64;
+    __shared__ __align__(16) float stage[ROWS * STAGE2_PITCH];
 
     int g = blockIdx.x, b, strip;
     if (xcd_map) {
@@ -356,58 +380,80 @@ __global__ __launch_bounds__(ROWS2 * 64) void k_table_build2(const float *__rest
         strip = g % strips;
         b = g / strips;
     }
-    const int i0 = strip * ROWS2;
+    const int i0 = strip * ROWS;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = i0 + wave;
+    const int seg = lane ^ 15;                          // input segment of this lane
+    const int x0 = seg * R;
 
-    for (int t = threadIdx.x; t < WORDS; t += THREADS) sbits[t] = signs[(size_t)b * WORDS + t];
-    __syncthreads();
-
-    // signed, zero-padded row in the order x = q 64 + (lane ^ 15)
+    // signed, zero-padded row: 64 (R) consecutive elements per lane
     float v[R];
-    const int rowc = row < m ? row : m - 1;
-    const int lx = lane ^ 15;
+    {
+        // sign bits of elements x0 .. x0 + R - 1 (R >= 32: whole words)
+        constexpr int SW = (R + 31) / 32;
+        uint32_t sw[SW];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int x = q * 64 + lx;
-        const int xc = x < n ? x : n - 1;
-        const float a = A[(size_t)rowc * n + xc];
-        const uint32_t bit = (sbits[x >> 5] >> (x & 31)) & 1u;
-        v[q] = (row < m && x < n) ? (bit ? -a : a) : 0.f;
+        for (int w = 0; w < SW; ++w) sw[w] = signs[(size_t)b * WORDS + (x0 >> 5) + w];
+        if constexpr (R < 32) sw[0] >>= (x0 & 31);
+        const bool live = row < m && x0 < n;
+        const float *src = A + (size_t)(row < m ? row : 0) * n + x0;
+        if (live && x0 + R <= n && (n & 3) == 0) {
+            // whole segment inside the row: 16-byte loads
+            const float4 *s4 = reinterpret_cast<const float4 *>(src);
+#pragma unroll
+            for (int j = 0; j < R / 4; ++j) {
+                const float4 t = s4[j];
+                v[4 * j] = t.x;
+                v[4 * j + 1] = t.y;
+                v[4 * j + 2] = t.z;
+                v[4 * j + 3] = t.w;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q] = (live && x0 + q < n) ? src[q] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            v[q] = __uint_as_float(__float_as_uint(v[q]) ^ (((sw[q >> 5] >> (q & 31)) & 1u) << 31));
     }
     fwht_wave2<LOGD>(v);
 
-    using S = Store<DT>;
-    constexpr int PACK = S::ROWS;                       // rows per 32-bit store
-    constexpr int TPC = ROWS2 / PACK;                   // threads per column
+    constexpr int TPC = ROWS / PACK;                   // threads per column
     constexpr int CPP = THREADS / TPC;                  // columns per pass
-    float scale[PACK];
-    const int my_rows = (threadIdx.x % TPC) * PACK;
+    const int half = threadIdx.x % TPC, my_rows = half * PACK;
+    float inv_scale[PACK];
 #pragma unroll
-    for (int r = 0; r < PACK; ++r) scale[r] = scales[i0 + my_rows + r];
-    uint32_t *out32 = reinterpret_cast<uint32_t *>(table);
-    const size_t col_words = (size_t)pitch * (DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1) / 4;
-    // column-local index of register j of a chunk in this lane, and its slot
-    const int wl_lane = (lane & 15) | ((lane >> 4) & 3) << 6;
+    for (int r = 0; r < PACK; ++r) inv_scale[r] = 1.0f / scales[i0 + my_rows + r];
+    constexpr int BT = DT == KERDOCK_F32 ? 4 : DT == KERDOCK_BF16 ? 2 : 1;
+    unsigned char *out = reinterpret_cast<unsigned char *>(table);
+    const size_t col_bytes = (size_t)pitch * BT;
+    // output index of register q in this lane, less its register bits
+    constexpr int LR = LOGD - 6;
+    const int w_lane = ((lane >> 4) & 1) | ((lane >> 5) & 1) << 1 | (lane & 15) << LR;
 
 #pragma unroll
     for (int c = 0; c < R / QC; ++c) {
+        // chunk c: the registers whose output lies in columns [c COLS, (c+1) COLS)
 #pragma unroll
-        for (int j = 0; j < QC; ++j) {
-            const int wl = wl_lane | (j & 3) << 4 | (j >> 2) << 8;
-            stage[(wl + 16 * (wl >> 6)) * P2 + wave] = v[c * QC + j];
+        for (int q = 0; q < R; ++q) {
+            if ((((q & 3) << (LR + 4)) >> 10) != c) continue;   // w >> 10, as w_lane < 1024
+            const int w = w_lane | (q & (R - 4)) | (q & 3) << (LR + 4);
+            const int wl = w & (COLS - 1);
+            const int slot = wl ^ (((wl >> 6) & 15) << 2);
+            stage[wave * STAGE2_PITCH + slot] = v[q];
         }
         lds_barrier();
+        const size_t colbase = (size_t)b * D + (size_t)c * COLS;
         for (int cc = threadIdx.x / TPC; cc < COLS; cc += CPP) {
-            const float *src = stage + (cc + 16 * (cc >> 6)) * P2 + my_rows;
+            const int slot = cc ^ (((cc >> 6) & 15) << 2);
             float vals[PACK];
 #pragma unroll
             for (int r = 0; r < PACK; ++r) {
-                if constexpr (DT == KERDOCK_FP8E4M3) vals[r] = src[r] / scale[r];
-                else vals[r] = src[r];
+                const float t = stage[(my_rows + r) * STAGE2_PITCH + slot];
+                vals[r] = DT == KERDOCK_FP8E4M3 ? t * inv_scale[r] : t;
             }
-            const size_t col = (size_t)b * D + (size_t)c * COLS + cc;
-            out32[col * col_words + (size_t)(i0 + my_rows) / PACK] = S::pack(vals);
+            unsigned char *dst = out + (colbase + cc) * col_bytes + (size_t)(i0 + my_rows) * BT;
+            store_rows<DT, PACK>(dst, vals);
         }
         lds_barrier();
     }
@@ -443,7 +489,7 @@ __global__ __launch_bounds__(256) void k_identity_block(const float *__restrict_
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int ii = part * ROWS + r;
-            vals[r] = tile[ii][c] / scales[i0 + ii];
+            vals[r] = tile[ii][c] * (1.0f / scales[i0 + ii]);
         }
         out32[(base_col + w) * col_words + (size_t)(i0 + part * ROWS) / ROWS] = S::pack(vals);
     }
@@ -498,19 +544,38 @@ int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dt
     return KERDOCK_OK;
 }
 
+// rows per workgroup and rows per store of k_table_build2.  The write rate
+// follows the length of the column segment one workgroup writes (measured
+// on the n = 2048, m = 2048 tables: 32-byte segments about 1.9 TB/s, 64-byte
+// segments about 3.3 TB/s), so FP32 takes 16 rows (one workgroup per CU at
+// its register count); BF16 measured the same with 8 or 16 rows (19 ms) and
+// FP8 is bound by its conversions, where 8-row workgroups (two or more per
+// CU) overlap one's stores with another's arithmetic.
+template <int DT> struct Build2Shape {
+    static constexpr int ROWS = DT == KERDOCK_F32 ? 16 : 8;
+    static constexpr int PACK = DT == KERDOCK_BF16 ? 4 : DT == KERDOCK_F32 ? 4 : 8;
+};
+
+template <int LOGD, int DT, int ROWS, int PACK>
+static int launch_build2(const float *A, int m, int n, int pitch, const uint32_t *signs, const float *scales,
+                         void *table, hipStream_t s) {
+    const int nb = (1 << LOGD) / 2;
+    const int strips = pitch / ROWS;
+    const int xcd_map = (strips % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_table_build2<LOGD, DT, ROWS, PACK>), dim3(strips * nb), dim3(ROWS * 64), 0, s, A, m, n,
+                       pitch, signs, scales, table, strips, xcd_map);
+    KD_LAUNCH("k_table_build2");
+    return KERDOCK_OK;
+}
+
 template <int LOGD, int DT>
 static int build_kd(const float *A, int m, int n, int pitch, const uint32_t *signs,
                     const float *scales, void *table, hipStream_t s) {
     const int nb = (1 << LOGD) / 2;
     if constexpr (LOGD >= 8) {
-        if (build_variant() == 2) {
-            const int strips = pitch / ROWS2;
-            const int xcd_map = (strips % 8 == 0) ? 1 : 0;
-            hipLaunchKernelGGL((k_table_build2<LOGD, DT>), dim3(strips * nb), dim3(ROWS2 * 64), 0, s, A, m, n, pitch,
-                               signs, scales, table, strips, xcd_map);
-            KD_LAUNCH("k_table_build2");
-            return KERDOCK_OK;
-        }
+        if (build_variant() == 2)
+            return launch_build2<LOGD, DT, Build2Shape<DT>::ROWS, Build2Shape<DT>::PACK>(A, m, n, pitch, signs,
+                                                                                        scales, table, s);
     }
     const int strips = pitch / BuildShape<DT>::ROWS;
     const int xcd_map = (strips % 8 == 0) ? 1 : 0;

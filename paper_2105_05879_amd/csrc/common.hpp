@@ -52,29 +52,6 @@ __device__ __forceinline__ float bf16_to_f32(uint32_t h16) {
     return __uint_as_float(h16 << 16);
 }
 
-// OCP FP8 E4M3 (bias 7, 3 mantissa bits, largest finite 448, no infinity):
-// round to nearest even, saturate to +-448.  The quantum of |v| in
-// [2^e, 2^(e+1)) is 2^(e-3) (e >= -6); below 2^-6 the quantum is 2^-9.
-__device__ __forceinline__ uint8_t f32_to_e4m3_sat(float v) {
-    uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
-    float a = fabsf(v);
-    if (!(a < 464.0f)) return (uint8_t)(sign | 0x7Eu);   // >= 464 (and NaN) -> 448
-    int e = (int)((__float_as_uint(a) >> 23) & 0xFF) - 127;
-    if (e < -6) e = -6;
-    float q = __uint_as_float((uint32_t)(e - 3 + 127) << 23);   // 2^(e-3), exact
-    float r = rintf(a / q) * q;                                  // RNE, exact
-    if (r >= 448.0f) return (uint8_t)(sign | 0x7Eu);
-    uint32_t rb = __float_as_uint(r);
-    int re = (int)((rb >> 23) & 0xFF) - 127;
-    if (r == 0.0f) return (uint8_t)sign;
-    if (re < -6) {                                      // subnormal: r = mant * 2^-9
-        uint32_t mant = (uint32_t)(r * 512.0f);
-        return (uint8_t)(sign | mant);
-    }
-    uint32_t mant = (rb >> 20) & 0x7u;
-    return (uint8_t)(sign | ((uint32_t)(re + 7) << 3) | mant);
-}
-
 // E4M3 byte -> FP32.  Normal codes: move exponent and mantissa into an FP32
 // word and add 120 to the exponent (bias 127 - 7).  Subnormal codes (exponent
 // field 0): mantissa * 2^-9.  No FP32 denormal is ever formed.
