@@ -31,6 +31,9 @@ HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
 METRIC = "thresholded-Ax/sec at n=2048, eps=0.05: plain vs BF16/batched/learned; % HBM peak"
 N_GRID = [8192, 12288, 16384, 20480, 24576, 28672, 32768, 40960, 49152, 65536, 98304, 131072]
 BYTES = {"f32": 4, "bf16": 2, "fp8": 1}
+# vector ALU issue rate of the chip: 256 CUs x 4 SIMDs, one 64-lane wave
+# instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 PLANTED_GRID = [512, 1024, 2048, 4096, 8192, 16384, 32768, 65536]
 MU_F32 = {}          # mu-hat of the FP32 table (first vectors), the reference of the other table types
 
@@ -78,7 +81,11 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
     torch.cuda.synchronize()
     prep = time.perf_counter() - t0
     info = h.info
-    log("%s: prepare %.3f s, table %.1f GB" % (dt, prep, info.table_bytes / 1e9))
+    proof = prepare_roofline(info, dt)
+    log("%s: prepare %.3f s, table %.1f GB, construction kernels %.2f ms = %.0f GB/s written%s"
+        % (dt, prep, info.table_bytes / 1e9, info.build_ms, proof["write_GBps"] if proof else 0,
+           (", VALU issue %.0f%% busy" % (100 * proof["frac_valu_issue"]))
+           if proof and proof["frac_valu_issue"] else ""))
     if args.J and args.K:
         J, K, rc = args.J, args.K, float("nan")
     else:
@@ -165,6 +172,7 @@ def time_form(kd, torch, np, A, X, Xc, A64, X64, supports, sup_c, Ax, dt, args):
         "x_per_s": B * args.steps / el, "ms_per_step": el / args.steps * 1e3, "J": J, "K": K, "N": N,
         "calib_recall": rc, "recall_mean": float(np.mean(rec)), "recall_min": float(np.min(rec)),
         "max_abs_err_vs_fp64": err, "prepare_s": prep, "table_GB": info.table_bytes / 1e9,
+        "prepare_roofline": proof,
         "kernel_ms": {"draws_sort": kern[0], "gather": kern[1], "select": kern[2], "survivors": kern[3]},
         "gather_GBps": gbps, "gather_frac_hbm": gbps / HBM_PEAK_GBPS,
         "gather_bytes_per_launch": gather_bytes, "shared_draws": shared, "autotuned": tuned,
@@ -816,6 +824,51 @@ def cpu_baseline(A64, X64, J, K, eps, s_max, seed):
     return {"value": P / (el * N / Np), "unit": "thresholded-Ax/s", "cores": P, "kind": "oracle",
             "sample": "%d vectors of the timed batch, %d draws each (J=%d, K=%d) instead of N=%d; "
                       "%.1f s measured, rate scaled by %d/%d" % (P, Np, Jp, Kp, N, el, Np, N)}
+
+
+def build_counters(dt):
+    """SQ_INSTS_VALU and HBM bytes of the table build (k_table_build2 for
+    d >= 256) of the n = m = 2048 table of this dtype, from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source;
+    else None."""
+    path = os.path.join(ROOT, "profiles", "table_build_n2048_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ": " in line:
+            k, v = line.strip().split(": ", 1)
+            rec[k] = v
+    src = open(os.path.join(ROOT, "paper_2105_05879_amd", "csrc", "build_kernels.hip"), "rb").read()
+    if rec.get("build_kernels_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    out = {}
+    for key in ("valu_instr", "fetch_bytes", "write_bytes"):
+        if "%s_%s" % (key, dt) in rec:
+            out[key] = float(rec["%s_%s" % (key, dt)])
+    return out or None
+
+
+def prepare_roofline(info, dt):
+    """The table build against its two ceilings: HBM writes (the table's
+    bytes at 8 TB/s) and vector-ALU issue (its counted VALU instructions at
+    the chip's issue rate); its kernel time comes from the library (HIP events
+    around the construction kernels inside kerdock_prepare)."""
+    ms = info.build_ms
+    if not ms > 0:
+        return None
+    gbps = info.table_bytes / (ms * 1e-3) / 1e9
+    r = {"table_build_ms": ms, "table_bytes": info.table_bytes, "write_GBps": gbps,
+         "frac_hbm_write": gbps / HBM_PEAK_GBPS, "valu_issue_ms": None, "frac_valu_issue": None,
+         "hbm_bytes": None}
+    c = build_counters(dt)
+    if c and "valu_instr" in c:
+        r["valu_issue_ms"] = c["valu_instr"] / VALU_WAVE_INSTR_PER_S * 1e3
+        r["frac_valu_issue"] = r["valu_issue_ms"] / ms
+    if c and "fetch_bytes" in c and "write_bytes" in c:
+        r["hbm_bytes"] = c["fetch_bytes"] + c["write_bytes"]
+    r["bound"] = "alu" if (r["frac_valu_issue"] or 0) > r["frac_hbm_write"] else "hbm"
+    return r
 
 
 def traffic_from_profiles(dt):

@@ -65,6 +65,8 @@ typedef struct {
     uint32_t field_poly;   /* irreducible polynomial of F_{2^{k-1}} (bits)   */
     kerdock_dtype dtype;
     size_t table_bytes;    /* bytes of the sketch table in device memory      */
+    float build_ms;        /* device time of the table construction kernels
+                              in kerdock_prepare (HIP events around them)    */
 } kerdock_info;
 
 /* Streaming parameters (Algorithm 1 streaming step, Theorem 5).  A zeroed
@@ -142,7 +144,9 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
  * even K); selects S = the s_max rows of largest |mu| (ties: smaller index),
  * optionally only those with |mu| >= tau; computes a_i.x for i in S and
  * keeps |a_i.x| >= eps.  May grow the handle's workspace (hipMalloc) unless
- * kerdock_reserve was called with sizes at least as large.
+ * kerdock_reserve was called with sizes at least as large.  Calls on one
+ * handle share its workspace: calls that overlap in time on one handle race
+ * and must be serialised by the caller.
  * Errors: NOT_PREPARED, INVALID_ARG (NULL pointers with batch > 0, eps <= 0
  * or NaN, s_max out of range, J < 1, K < 1, K > 32, J K > 2^31), OOM, HIP.
  */

@@ -280,15 +280,15 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     }
     dg.dbg_coef = p->dbg_coef;
     dg.active = active;
+    SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, active};
+    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr,
+                svals, surv_vec4(X, h->n), h->m, row_ws};
     if (dg.bucket) rc = launch_draw_sort(dg, batch, K, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
     if (rc == KERDOCK_OK) rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
-    SelArgs sa{partial, h->m, h->pitch, K, cpb, J, h->scales, s_max, p->tau, p->dbg_mu, surv, nsurv, active};
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
-    SurvArgs va{h->A, h->n, X, surv, nsurv, s_max, eps, out_idx, out_val, out_cnt, p->dbg_values, active, nullptr,
-                svals, surv_vec4(X, h->n), h->m, row_ws};
     if (rc == KERDOCK_OK) rc = launch_survivors(va, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[4], s));
     if (rc != KERDOCK_OK) return rc;
@@ -315,6 +315,7 @@ int apply_internal(kerdock_handle h, const float *X, int batch, float eps, int s
 static __device__ __align__(256) unsigned char scratch[KERDOCK_STATIC_SCRATCH_BYTES];
 
 constexpr int MAX_DEVICES = 64;
+
 static std::mutex g_scratch_mu;
 static void *g_scratch_ptr[MAX_DEVICES];
 
@@ -506,9 +507,21 @@ int kerdock_prepare(const float *A, int m, int n, kerdock_dtype dtype, void *str
     if (rc == KERDOCK_OK && (e = hipMalloc((void **)&norm2, (size_t)h->pitch * 4)) != hipSuccess)
         rc = fail(KERDOCK_ERR_OOM, "row norms");
     if (rc == KERDOCK_OK) rc = launch_row_scales(h->A, m, n, h->pitch, h->d, dtype, h->scales, norm2, s);
+    // the construction kernels are timed with a pair of events (their
+    // failure to be created only leaves build_ms at 0)
+    hipEvent_t tb[2] = {nullptr, nullptr};
+    const bool timed = hipEventCreate(&tb[0]) == hipSuccess && hipEventCreate(&tb[1]) == hipSuccess;
+    if (rc == KERDOCK_OK && timed && (e = hipEventRecord(tb[0], s)) != hipSuccess) rc = hip_fail(e, "event");
     if (rc == KERDOCK_OK)
         rc = launch_table_build(dtype, h->k, h->A, m, n, h->pitch, h->signs, h->scales, h->table, s);
+    if (rc == KERDOCK_OK && timed && (e = hipEventRecord(tb[1], s)) != hipSuccess) rc = hip_fail(e, "event");
     if (rc == KERDOCK_OK && (e = hipStreamSynchronize(s)) != hipSuccess) rc = hip_fail(e, "prepare");
+    if (rc == KERDOCK_OK && timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, tb[0], tb[1]) == hipSuccess) h->build_ms = ms;
+    }
+    for (hipEvent_t ev : tb)
+        if (ev) (void)hipEventDestroy(ev);
     if (rc == KERDOCK_OK) {
         std::vector<float> rn((size_t)m);
         if ((e = hipMemcpy(rn.data(), norm2, (size_t)m * 4, hipMemcpyDeviceToHost)) != hipSuccess)
@@ -644,6 +657,7 @@ int kerdock_query(kerdock_handle h, kerdock_info *info) {
     info->field_poly = h->poly;
     info->dtype = h->dtype;
     info->table_bytes = h->table_bytes;
+    info->build_ms = h->build_ms;
     return KERDOCK_OK;
 }
 

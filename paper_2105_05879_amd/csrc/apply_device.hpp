@@ -675,15 +675,28 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
 #pragma unroll
                 for (int ti = 0; ti < TILES; ++ti) accumulate<DT>(acc[ti], raw[u][ti], cc[u]);
         }
-        for (; j < cnt; j += gstride) {
-            const uint32_t l = s_ell[j];
-            const float c = s_coef[j];
-            const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
+        if (j < cnt) {
+            // the last draws (fewer than UNROLL): their loads issued
+            // together, accumulated in the same order
+            u32x4 raw[UNROLL][TILES];
+            float cc[UNROLL];
 #pragma unroll
-            for (int ti = 0; ti < TILES; ++ti)
-                if (tile_on[ti])
-                    accumulate<DT>(acc[ti], __builtin_nontemporal_load(
-                                                reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES)), c);
+            for (int u = 0; u < UNROLL; ++u) {
+                const bool on = j + u * gstride < cnt;
+                const uint32_t l = on ? s_ell[j + u * gstride] : 0u;
+                cc[u] = on ? s_coef[j + u * gstride] : 0.f;
+                const unsigned char *colp = base + (size_t)l * (size_t)col_bytes;
+#pragma unroll
+                for (int ti = 0; ti < TILES; ++ti)
+                    raw[u][ti] = (on && tile_on[ti]) ? __builtin_nontemporal_load(
+                                                           reinterpret_cast<const u32x4 *>(colp + ti * TILE_BYTES))
+                                                     : u32x4{0u, 0u, 0u, 0u};
+            }
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+                if (j + u * gstride < cnt)
+#pragma unroll
+                    for (int ti = 0; ti < TILES; ++ti) accumulate<DT>(acc[ti], raw[u][ti], cc[u]);
         }
     }
 
@@ -719,6 +732,8 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
 // and written in ascending row order.
 constexpr int SELECT_THREADS = 1024;
 
+// TH threads (a multiple of 64); sh holds TH / 64 + 1 ints
+template <int TH = SELECT_THREADS>
 __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int incl = v;
@@ -731,16 +746,16 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh) 
     __syncthreads();
     if (threadIdx.x == 0) {
         int run = 0;
-        for (int w = 0; w < SELECT_THREADS / 64; ++w) {
+        for (int w = 0; w < TH / 64; ++w) {
             const int c = sh[w];
             sh[w] = run;
             run += c;
         }
-        sh[SELECT_THREADS / 64] = run;
+        sh[TH / 64] = run;
     }
     __syncthreads();
     const int res = sh[wave] + incl - v;
-    *total = sh[SELECT_THREADS / 64];
+    *total = sh[TH / 64];
     __syncthreads();
     return res;
 }
@@ -748,7 +763,9 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *total, int *sh) 
 // The s_max largest keys (ties: smaller index), optionally only keys >=
 // tau_bits, written in ascending index order to surv_row (padded with -1),
 // their number to *nsurv_out.  Radix select over the 32-bit keys in LDS
-// (8 bits per round, histogram in LDS), then two block-wide scans.
+// (8 bits per round, histogram in LDS), then two block-wide scans; TH >= 256
+// threads (the result does not depend on TH).
+template <int TH = SELECT_THREADS>
 __device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max, uint32_t tau_bits,
                                            int32_t *surv_row, int32_t *nsurv_out, uint32_t *hist,
                                            int *scan_sh, uint32_t *sel_state) {
@@ -760,7 +777,7 @@ __device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max
         for (int shift = 24; shift >= 0; shift -= 8) {
             if (threadIdx.x < 256) hist[threadIdx.x] = 0;
             __syncthreads();
-            for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
+            for (int i = threadIdx.x; i < m; i += TH) {
                 const uint32_t kk = key[i];
                 if (((kk ^ prefix) & fixed) == 0) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
             }
@@ -801,13 +818,13 @@ __device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max
     const uint32_t theta = prefix;
 
     // ascending compaction: thread owns rows [i0, i1)
-    const int per = (m + SELECT_THREADS - 1) / SELECT_THREADS;
+    const int per = (m + TH - 1) / TH;
     const int i0 = min(m, (int)threadIdx.x * per), i1 = min(m, i0 + per);
     int eq_local = 0;
     if (!take_all)
         for (int i = i0; i < i1; ++i) eq_local += key[i] == theta;
     int eq_total;
-    int eq_rank = block_exclusive_scan(eq_local, &eq_total, scan_sh);
+    int eq_rank = block_exclusive_scan<TH>(eq_local, &eq_total, scan_sh);
     int sel_local = 0;
     {
         int er = eq_rank;
@@ -820,7 +837,7 @@ __device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max
         }
     }
     int total;
-    int pos = block_exclusive_scan(sel_local, &total, scan_sh);
+    int pos = block_exclusive_scan<TH>(sel_local, &total, scan_sh);
     {
         int er = eq_rank;
         for (int i = i0; i < i1; ++i) {
@@ -832,7 +849,7 @@ __device__ __forceinline__ void select_top(const uint32_t *key, int m, int s_max
         }
     }
     total = min(total, s_max);
-    for (int s = total + threadIdx.x; s < s_max; s += SELECT_THREADS) surv_row[s] = -1;
+    for (int s = total + threadIdx.x; s < s_max; s += TH) surv_row[s] = -1;
     if (threadIdx.x == 0) *nsurv_out = total;
 }
 
@@ -850,8 +867,9 @@ struct SelArgs {
     const int32_t *active;    // optional [batch]: vectors with 0 are skipped
 };
 
-// shared memory: key[m], hist[256], scan_sh[SELECT_THREADS/64 + 1], sel_state[2]
-template <int KMAX>
+// shared memory: key[m], hist[256], scan_sh[TH/64 + 1], sel_state[2]; TH
+// threads (the result does not depend on TH)
+template <int KMAX, int TH = SELECT_THREADS>
 __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *key, uint32_t *hist,
                                            int *scan_sh, uint32_t *sel_state) {
     const float *__restrict__ partial = a.partial;
@@ -865,7 +883,7 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
     if (a.active && !a.active[t]) return;      // uniform over the workgroup
     const int nchunks = K * chunks_per_batch;
     const float *pt = partial + (size_t)t * nchunks * pitch;
-    for (int i = threadIdx.x; i < m; i += SELECT_THREADS) {
+    for (int i = threadIdx.x; i < m; i += TH) {
         float v[KMAX];
 #pragma unroll
         for (int a = 0; a < KMAX; ++a) {
@@ -915,8 +933,8 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
         key[i] = __float_as_uint(fabsf(med));
     }
     __syncthreads();
-    select_top(key, m, s_max, __float_as_uint(fmaxf(tau, 0.f)), surv + (size_t)t * s_max, nsurv + t, hist,
-               scan_sh, sel_state);
+    select_top<TH>(key, m, s_max, __float_as_uint(fmaxf(tau, 0.f)), surv + (size_t)t * s_max, nsurv + t, hist,
+                   scan_sh, sel_state);
 }
 
 // ------------------------------------------------------------- survivors --

@@ -107,4 +107,5 @@ struct kerdock_handle_s {
     int tune_bucket = -1;         // group draws by basis: 1 / 0, -1: the default rule
     kerdock_learned_s *learned = nullptr;   // attached learned-proposal state
     float row_norm2_max = 0.f;    // |A|_{2->inf}^2: largest squared row norm
+    float build_ms = 0.f;         // device time of the table construction kernels
 };

@@ -43,7 +43,7 @@ class Info(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("d", ctypes.c_int32), ("L", ctypes.c_int64), ("pitch", ctypes.c_int32),
                 ("field_poly", ctypes.c_uint32), ("dtype", ctypes.c_int),
-                ("table_bytes", ctypes.c_size_t)]
+                ("table_bytes", ctypes.c_size_t), ("build_ms", ctypes.c_float)]
 
 
 EXPORTS = {
