@@ -883,54 +883,74 @@ __device__ __forceinline__ void select_vec(const SelArgs &a, int t, uint32_t *ke
     if (a.active && !a.active[t]) return;      // uniform over the workgroup
     const int nchunks = K * chunks_per_batch;
     const float *pt = partial + (size_t)t * nchunks * pitch;
-    for (int i = threadIdx.x; i < m; i += TH) {
-        float v[KMAX];
+    // R rows per thread (i0 + r TH) with all their loads of a round issued
+    // together; each row's partials are still summed in chunk order
+    constexpr int R = KMAX <= 8 ? 4 : 1;
+    for (int i0 = threadIdx.x; i0 < m; i0 += R * TH) {
+        float v[R][KMAX];
 #pragma unroll
         for (int a = 0; a < KMAX; ++a) {
-            float s = INFINITY;
+            float sr[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) sr[r] = INFINITY;
             if (a < K) {
-                // partials of batch a summed in chunk order; eight loads in
-                // flight at a time
-                const float *pa = pt + (size_t)a * chunks_per_batch * pitch + i;
-                s = 0.f;
+                const float *pa = pt + (size_t)a * chunks_per_batch * pitch;
+#pragma unroll
+                for (int r = 0; r < R; ++r) sr[r] = 0.f;
                 int c = 0;
                 for (; c + 8 <= chunks_per_batch; c += 8) {
-                    float q[8];
+                    float q[R][8];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) q[u] = pa[(size_t)(c + u) * pitch];
+                    for (int r = 0; r < R; ++r) {
+                        const int i = min(i0 + r * TH, m - 1);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) s += q[u];
-                }
-                for (; c < chunks_per_batch; ++c) s += pa[(size_t)c * pitch];
-                s = s / (float)J;
-            }
-            v[a] = s;
-        }
-        // bitonic sort, ascending
-#pragma unroll
-        for (int size = 2; size <= KMAX; size <<= 1)
-#pragma unroll
-            for (int stride = size >> 1; stride > 0; stride >>= 1)
-#pragma unroll
-                for (int a = 0; a < KMAX; ++a) {
-                    const int bb = a ^ stride;
-                    if (bb > a) {
-                        const bool up = (a & size) == 0;
-                        const float lo = fminf(v[a], v[bb]), hi = fmaxf(v[a], v[bb]);
-                        v[a] = up ? lo : hi;
-                        v[bb] = up ? hi : lo;
+                        for (int u = 0; u < 8; ++u) q[r][u] = pa[(size_t)(c + u) * pitch + i];
                     }
-                }
-        float lo_mid = 0.f, hi_mid = 0.f;
 #pragma unroll
-        for (int a = 0; a < KMAX; ++a) {
-            if (a == (K - 1) / 2) lo_mid = v[a];
-            if (a == K / 2) hi_mid = v[a];
+                    for (int r = 0; r < R; ++r)
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) sr[r] += q[r][u];
+                }
+                for (; c < chunks_per_batch; ++c) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) sr[r] += pa[(size_t)c * pitch + min(i0 + r * TH, m - 1)];
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) sr[r] = sr[r] / (float)J;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r][a] = sr[r];
         }
-        float med = (K & 1) ? hi_mid : 0.5f * (lo_mid + hi_mid);
-        med *= scales[i];
-        if (mu_out) mu_out[(size_t)t * m + i] = med;
-        key[i] = __float_as_uint(fabsf(med));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = i0 + r * TH;
+            if (i >= m) break;
+            // bitonic sort, ascending
+#pragma unroll
+            for (int size = 2; size <= KMAX; size <<= 1)
+#pragma unroll
+                for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+                    for (int a = 0; a < KMAX; ++a) {
+                        const int bb = a ^ stride;
+                        if (bb > a) {
+                            const bool up = (a & size) == 0;
+                            const float lo = fminf(v[r][a], v[r][bb]), hi = fmaxf(v[r][a], v[r][bb]);
+                            v[r][a] = up ? lo : hi;
+                            v[r][bb] = up ? hi : lo;
+                        }
+                    }
+            float lo_mid = 0.f, hi_mid = 0.f;
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) {
+                if (a == (K - 1) / 2) lo_mid = v[r][a];
+                if (a == K / 2) hi_mid = v[r][a];
+            }
+            float med = (K & 1) ? hi_mid : 0.5f * (lo_mid + hi_mid);
+            med *= scales[i];
+            if (mu_out) mu_out[(size_t)t * m + i] = med;
+            key[i] = __float_as_uint(fabsf(med));
+        }
     }
     __syncthreads();
     select_top<TH>(key, m, s_max, __float_as_uint(fmaxf(tau, 0.f)), surv + (size_t)t * s_max, nsurv + t, hist,
@@ -1032,16 +1052,25 @@ __device__ __forceinline__ float survivor_dot(const float *__restrict__ row, con
     const int lane = threadIdx.x & 63;
     float p[4] = {0.f, 0.f, 0.f, 0.f}, e[4] = {0.f, 0.f, 0.f, 0.f};
     if (vec4) {
+        // n <= 4096: at most 16 pieces per lane, all loaded before the steps
         const float4 *__restrict__ r4 = reinterpret_cast<const float4 *>(row);
         const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
         const int n4 = n >> 2;
-#pragma unroll 4
-        for (int q = lane; q < n4; q += 64) {
-            const float4 a = r4[q], b = x4[q];
-            dot_step(p[0], e[0], a.x, b.x);
-            dot_step(p[1], e[1], a.y, b.y);
-            dot_step(p[2], e[2], a.z, b.z);
-            dot_step(p[3], e[3], a.w, b.w);
+        float4 ra[16], xa[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int q = lane + 64 * i;
+            ra[i] = q < n4 ? r4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            xa[i] = q < n4 ? x4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (lane + 64 * i < n4) {
+                dot_step(p[0], e[0], ra[i].x, xa[i].x);
+                dot_step(p[1], e[1], ra[i].y, xa[i].y);
+                dot_step(p[2], e[2], ra[i].z, xa[i].z);
+                dot_step(p[3], e[3], ra[i].w, xa[i].w);
+            }
         }
     } else {
         for (int q = lane; q < n; q += 64) dot_step(p[0], e[0], row[q], x[q]);
