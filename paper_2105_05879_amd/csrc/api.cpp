@@ -37,6 +37,7 @@ int launch_shared_coef(kerdock_dtype dt, const float *X, int batch, int n, int k
                        float *coef, uint32_t *dbg_samples, float *dbg_coef, hipStream_t s);
 size_t shared_coef_floats(kerdock_dtype dt, int batch, int J, int K);
 int shared_n_pad(int n);
+size_t shared_digit_bytes(int batch, int n);
 int shared_splits(int J);
 int launch_shared_gemm(kerdock_dtype dt, const void *table, int pitch, int batch, int J, int K, const uint32_t *ell,
                        const float *coef, float *partial, hipStream_t s);
@@ -583,7 +584,7 @@ int kerdock_sparse_apply_shared(kerdock_handle h, const float *X, int batch, flo
     const size_t o_surv = off;    off += align256((size_t)batch * s_max * 4);
     const size_t o_nsurv = off;   off += align256((size_t)batch * 4);
     const size_t o_svals = off;   off += align256((size_t)batch * s_max * 4);
-    const size_t o_digits = off;  off += align256((size_t)batch * 4 * shared_n_pad(h->n));
+    const size_t o_digits = off;  off += align256(shared_digit_bytes(batch, h->n));
     const size_t o_xscale = off;  off += align256((size_t)batch * 8);
     const size_t o_rows = off;    off += align256(survivor_rows_bytes(batch, h->m, s_max));
     int rc = ensure_workspace(h, off);

@@ -25,6 +25,19 @@ namespace kd {
 int shared_n_pad(int n) { return (n + 63) / 64 * 64; }
 
 constexpr int ST = KERDOCK_SHARED_TILE;       // vectors per draw group
+
+// Digits in the order the coefficient MFMAs read them: for group g, digit
+// plane b and step s (coordinates 64 s .. + 63), a 4 KiB block of 4 wave
+// blocks (vectors 16 w .. + 15) of 1 KiB, each [coordinate quarter (16
+// coordinates)][vector][16 coordinate bytes], so that lane l of wave w reads
+// bytes 16 l .. + 15 of its wave block as its B operand.
+__device__ __forceinline__ size_t digit_offset(int g, int b, int steps, int s, int tv, int c) {
+    return ((((size_t)g * 4 + b) * steps + s) << 12) + ((size_t)(tv >> 4) << 10) + ((size_t)(c >> 4) << 8) +
+           ((size_t)(tv & 15) << 4) + (size_t)(c & 15);
+}
+size_t shared_digit_bytes(int batch, int n) {
+    return (size_t)((batch + ST - 1) / ST) * ST * 4 * (size_t)shared_n_pad(n);
+}
 constexpr int SG_BM = 128;                    // table rows per GEMM workgroup
 constexpr int SG_BK = 32;                     // draws per LDS stage
 
@@ -39,9 +52,10 @@ constexpr int SG_BK = 32;                     // draws per LDS stage
 // so c = (sum_b 256^b C_b) 2^-E2 equals the per-vector form's exact signed sum.
 // Identity draws (basis d/2) give sqrt(d) x[w] directly.
 
-// k_x_digits: grid (batch), one wave.  digits[t][b][q] (q < n_pad, zero
-// beyond n) and xscale[t] = (scale exponent, flags): bit 0 x_t is finite,
-// bit 1 its top digit plane (b = 3) has a nonzero digit.
+// k_x_digits: grid (batch), one wave.  The digits of x_t at digit_offset
+// (coordinates q < n_pad, zero beyond n) and xscale[t] = (scale exponent,
+// flags): bit 0 x_t is finite, bit 1 its top digit plane (b = 3) has a
+// nonzero digit.
 template <int P>
 __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, int n, int n_pad,
                                                  int8_t *__restrict__ digits, int2 *__restrict__ xscale) {
@@ -50,7 +64,7 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
     int E2;
     bool finite;
     fixed_point<P>(X + (size_t)t * n, n, lane, xi, E2, finite);
-    int8_t *dt = digits + (size_t)t * 4 * n_pad;
+    const int g = t / ST, tv = t % ST, steps = n_pad / 64;
     uint32_t top = 0u;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -68,12 +82,15 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
                 packed[b][q / 4] |= (uint32_t)(uint8_t)dg << (8 * (q % 4));
             }
         }
+        // coordinates e0 .. e0 + 31: two 16-coordinate quarters of step e0 / 64
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            uint32_t *dst = reinterpret_cast<uint32_t *>(dt + (size_t)b * n_pad + e0);
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int w = 0; w < 8; ++w) dst[w] = packed[b][w];
-        }
+            for (int h = 0; h < 2; ++h) {
+                const int c = (e0 & 63) + 16 * h;
+                *reinterpret_cast<u32x4 *>(digits + digit_offset(g, b, steps, e0 / 64, tv, c)) =
+                    u32x4{packed[b][4 * h], packed[b][4 * h + 1], packed[b][4 * h + 2], packed[b][4 * h + 3]};
+            }
 #pragma unroll
         for (int w = 0; w < 8; ++w) top |= packed[3][w];
     }
@@ -84,8 +101,7 @@ __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, in
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int SC_DRAWS = 64;                  // draws per coefficient workgroup (16 per wave)
-constexpr int SC_LD = 80;                      // bytes per LDS row of 64 digits
+constexpr int SC_DRAWS = 64;                  // draws per coefficient workgroup
 
 // Sign bits to +-1 bytes: bit q of the 4-bit value m goes to byte q (the
 // four shifted copies m << 7 q do not overlap), then 0 -> 0x01, 1 -> 0xFF.
@@ -99,16 +115,18 @@ __device__ __forceinline__ int sign_bytes4(uint32_t m) {
 // batch).  Output layout: by_vector == 0, coef[g][j][t mod 64] (the 64
 // vectors of a draw contiguous); by_vector != 0, coef[g][t mod 64][kb JP + j
 // - kb J] with JP = J rounded up to 64 (the draws of a vector and batch
-// contiguous).  Wave w takes draws 16 w .. + 15 of the block (the 16 rows of
-// its MFMA blocks) against the group's 64 vectors (4 column blocks) and 4
-// digits: 16 accumulators.  Per step of 64 coordinates the digits of the 64
-// vectors go through LDS; the sign rows are made in registers from the sign
-// bitmaps and the Walsh pattern of w, sixteen coordinates (one 128-bit
-// operand) per lane; A and B give every lane the same 16 consecutive
-// coordinates of the step.  The next step's digits and sign word are loaded
-// before this step's MFMAs, with clamped indices (the only branch is the
-// wave-uniform skip of a zero top digit plane), so that no wait covers more
-// than the loads it needs.
+// contiguous).  Wave w takes the group's vectors 16 w .. + 15 (the 16
+// columns of its MFMA blocks) against all 64 draws of the block (4 row
+// blocks) and the 3 or 4 digit planes: 16 accumulators.  The sign rows of
+// the 64 draws are staged in LDS once (dynamic LDS: 64 (d/32 + 1) words, a
+// padded row per draw so that the 16 draws of a read meet distinct banks).
+// Per step of 64 coordinates wave w makes the +-1 sign operands of row
+// block w (from the staged sign words and the Walsh pattern of w) into a
+// double-buffered LDS tile that every wave then reads, one barrier per step;
+// a lane reads its 16-byte digit operands straight from memory (one
+// contiguous 1 KiB per wave and plane, in digit_offset order; a group's
+// digits stay in L2).  The next step's digits and sign operands are loaded
+// and made before this step's MFMAs.
 __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X, int n, int n_pad, int k, int64_t L,
                                                      const uint32_t *__restrict__ signs, uint64_t seed, int64_t t0,
                                                      int batch, int J, int K, int by_vector,
@@ -116,34 +134,48 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
                                                      const int2 *__restrict__ xscale, uint32_t *__restrict__ ell,
                                                      float *__restrict__ coef, uint32_t *__restrict__ dbg_samples,
                                                      float *__restrict__ dbg_coef) {
-    // [digit][vector][coordinate]; rows of 80 bytes (5 16-byte units), so
-    // that the 16 lanes of an operand read or a staging write meet 16
-    // distinct bank groups
-    __shared__ __align__(16) int8_t Bs[4][ST][SC_LD];
+    extern __shared__ uint32_t s_sign[];             // [64][words + 1]
+    __shared__ uint32_t s_l[SC_DRAWS];
+    __shared__ __align__(16) i32x4 s_a[2][4][64];   // sign operands [buffer][row block][lane]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = blockIdx.y, nx = min(ST, batch - g * ST);
-    const int d = 1 << k, words = d >= 32 ? d / 32 : 1;
-    // this lane's draw: row lane % 16 of the wave's block
-    const int row = lane & 15;
+    const int d = 1 << k, words = d >= 32 ? d / 32 : 1, wp = words + 1;
+    const int row = lane & 15;                       // draw row of a block / vector column
     const int N = J * K, JP = (J + 63) & ~63, jblocks = JP / SC_DRAWS;
-    const int kb = blockIdx.x / jblocks, jb0 = (blockIdx.x % jblocks) * SC_DRAWS + wave * 16;
-    const int jl = jb0 + row;
-    uint32_t my_l = 0;
-    if (jl < J) {
-        const int j = kb * J + jl;
-        uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + g), 1, 0};
-        philox4x64_10(c4, seed, 0);
-        const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
-        my_l = (uint32_t)__umul64hi(rr, (uint64_t)L);
+    const int kb = blockIdx.x / jblocks, jb0 = (blockIdx.x % jblocks) * SC_DRAWS;
+    const int kq = (lane >> 4) * 16;                 // this lane's 16 coordinates within a step
+    const int tv = wave * 16 + row;                  // this lane's vector column
+
+    // the block's draws (wave 0, one per lane) and their sign rows
+    if (tid < SC_DRAWS) {
+        const int jl = jb0 + tid;
+        uint32_t l = 0;
+        if (jl < J) {
+            const int j = kb * J + jl;
+            uint64_t c4[4] = {(uint64_t)(j >> 2), (uint64_t)(t0 + g), 1, 0};
+            philox4x64_10(c4, seed, 0);
+            const uint64_t rr = (j & 3) == 0 ? c4[0] : (j & 3) == 1 ? c4[1] : (j & 3) == 2 ? c4[2] : c4[3];
+            l = (uint32_t)__umul64hi(rr, (uint64_t)L);
+        }
+        s_l[tid] = l;
     }
-    const uint32_t bb = my_l >> k, ww = my_l & (uint32_t)(d - 1);
-    const bool krow = jl < J && (int)bb < d / 2;
-    const uint32_t sbase = krow ? bb * (uint32_t)words : 0u;      // a valid sign row for every lane
+    __syncthreads();
+    // only the words of coordinates below n_pad are read
+    const int wn = min(words, (n_pad + 31) / 32);
+    for (int i = tid; i < SC_DRAWS * wn; i += 256) {
+        const int r = i / wn, wi = i % wn;
+        const uint32_t bb = s_l[r] >> k;
+        s_sign[r * wp + wi] = (jb0 + r < J && (int)bb < d / 2) ? signs[bb * (uint32_t)words + wi] : 0u;
+    }
+    // the draw whose sign operands this lane makes: row `row` of block `wave`
+    const uint32_t my_l = s_l[wave * 16 + row];
+    const uint32_t ww = my_l & (uint32_t)(d - 1);
+    const bool krow = jb0 + wave * 16 + row < J && (int)(my_l >> k) < d / 2;
     const uint32_t w16 = (ww & 1u ? 0xAAAAu : 0u) ^ (ww & 2u ? 0xCCCCu : 0u) ^ (ww & 4u ? 0xF0F0u : 0u) ^
                          (ww & 8u ? 0xFF00u : 0u);
-    const int kq = (lane >> 4) * 16;                 // this lane's 16 coordinates within a step
+    const uint32_t *srow = s_sign + (wave * 16 + row) * wp;
 
-    i32x4 acc[4][4];                                 // [digit][column block]
+    i32x4 acc[4][4];                                 // [digit][row block]
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -151,100 +183,97 @@ __global__ __launch_bounds__(256) void k_shared_coef(const float *__restrict__ X
 
     // The top digit plane is skipped for a group whose vectors all have it
     // zero (typical for unit vectors: it only holds entries beyond about
-    // 2^23 of the fixed-point scale); its products would all be zero.
+    // 2^23 of the fixed-point scale); its products would all be zero.  (The
+    // barrier also completes the sign-row staging.)
     const bool top = __syncthreads_or(tid < nx && (xscale[g * ST + tid].y & 2)) != 0;
-    // staging of the digits: thread (vector tv_s, digit b_s) copies 64 bytes
-    const int tv_s = tid & 63, b_s = tid >> 6;
-    const bool stage = b_s < 3 || top;              // uniform per wave
-    const int8_t *dsrc = digits + ((size_t)(g * ST + min(tv_s, nx - 1)) * 4 + b_s) * n_pad;
+    // this lane's digit operands (columns past the batch end read the
+    // buffer's padding and are not written)
     const int steps = n_pad / 64;
-    u32x4 dg[4];
-    uint32_t wd;
-    // digits of step st for the LDS tile (waves that stage), and the sign
-    // word of this lane's draw (every wave)
+    const int8_t *dsrc = digits + digit_offset(g, 0, steps, 0, wave * 16, 0) + (size_t)lane * 16;
+    i32x4 dg[4];
     auto fetch = [&](int st) {
-        if (stage) {
-            const u32x4 *src = reinterpret_cast<const u32x4 *>(dsrc + st * 64);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) dg[u] = src[u];
-        }
-        wd = signs[sbase + min((st * 64 + kq) >> 5, words - 1)];
+        for (int b = 0; b < 4; ++b)
+            if (b < 3 || top) dg[b] = *reinterpret_cast<const i32x4 *>(dsrc + (((size_t)b * steps + st) << 12));
     };
-    fetch(0);
-    for (int st = 0; st < steps; ++st) {
-        if (stage) {
-            u32x4 *dst = reinterpret_cast<u32x4 *>(&Bs[b_s][tv_s][0]);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) dst[u] = dg[u];
-        }
+    // sign operand of this lane's draw at step st (coordinates past d, only
+    // when n_pad > d, meet zero digits)
+    auto make_sign = [&](int st) {
         const int q = st * 64 + kq;
-        // coordinates past d (only when n_pad > d) meet zero digits
+        const uint32_t wd = srow[min(q >> 5, words - 1)];
         const uint32_t par = __popc((uint32_t)q & ww) & 1u;
         const uint32_t m16 = ((wd >> (q & 31)) & 0xFFFFu) ^ w16 ^ (par ? 0xFFFFu : 0u);
         const bool on = krow && (q >> 5) < words;
-        const i32x4 a = on ? i32x4{sign_bytes4(m16 & 15u), sign_bytes4((m16 >> 4) & 15u),
-                                   sign_bytes4((m16 >> 8) & 15u), sign_bytes4(m16 >> 12)}
-                           : i32x4{0, 0, 0, 0};
-        __syncthreads();
-        fetch(min(st + 1, steps - 1));               // the last step reloads its own data
+        s_a[st & 1][wave][lane] = on ? i32x4{sign_bytes4(m16 & 15u), sign_bytes4((m16 >> 4) & 15u),
+                                             sign_bytes4((m16 >> 8) & 15u), sign_bytes4(m16 >> 12)}
+                                     : i32x4{0, 0, 0, 0};
+    };
+    fetch(0);
+    make_sign(0);
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        i32x4 a[4], bop[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int rb = 0; rb < 4; ++rb) a[rb] = s_a[st & 1][rb][lane];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bop[b] = dg[b];
+        if (st + 1 < steps) {
+            fetch(st + 1);
+            make_sign(st + 1);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 if (b == 3 && !top) continue;        // uniform
-                const i32x4 bop = *reinterpret_cast<const i32x4 *>(&Bs[b][c * 16 + row][kq]);
-                acc[b][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bop, acc[b][c], 0, 0, 0);
+                acc[b][rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rb], bop[b], acc[b][rb], 0, 0, 0);
             }
-        __syncthreads();
+        __syncthreads();                             // next buffer written; this one read
     }
 
-    // D block: lane holds draws 4 (lane / 16) + v of the wave's 16, vector
-    // column lane % 16 of block c
+    // D block rb: lane holds draws rb 16 + 4 (lane / 16) + v of the block,
+    // vector column lane % 16 of this wave
     const float sqrt_d = sqrtf((float)d);
-    float cv[4][4];                                  // [vector block][draw v]
+    const bool col_on = tv < nx;
+    const int t = g * ST + tv;
+    int2 sc = make_int2(0, 0);
+    if (col_on) sc = xscale[t];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int rr = 4 * (lane >> 4) + v;
-        const uint32_t l_r = __shfl(my_l, rr);
-        const int jr = kb * J + jb0 + rr;
+    for (int rb = 0; rb < 4; ++rb) {
+        float cv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) cv[c][v] = 0.f;
-        if (jb0 + rr >= J) continue;
-        const uint32_t b_r = l_r >> k, w_r = l_r & (uint32_t)(d - 1);
-        const bool ident = (int)b_r == d / 2;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int tv = c * 16 + row;
-            if (tv >= nx) continue;
-            const int t = g * ST + tv;
+        for (int v = 0; v < 4; ++v) {
+            const int rr = 4 * (lane >> 4) + v;          // row within the block
+            const uint32_t l_r = s_l[rb * 16 + rr];
+            const int jl = jb0 + rb * 16 + rr;
+            const int jr = kb * J + jl;
+            cv[v] = 0.f;
+            if (jl >= J) continue;
+            const uint32_t b_r = l_r >> k, w_r = l_r & (uint32_t)(d - 1);
+            const bool ident = (int)b_r == d / 2;
+            if (tv == 0) ell[(size_t)g * N + jr] = l_r;
+            if (!col_on) continue;
             float cf;
             if (ident) {
                 cf = ((int)w_r < n) ? sqrt_d * X[(size_t)t * n + w_r] : 0.f;
             } else {
-                const int2 sc = xscale[t];
-                const int64_t tot = (int64_t)acc[0][c][v] + ((int64_t)acc[1][c][v] << 8) +
-                                    ((int64_t)acc[2][c][v] << 16) + ((int64_t)acc[3][c][v] << 24);
+                const int64_t tot = (int64_t)acc[0][rb][v] + ((int64_t)acc[1][rb][v] << 8) +
+                                    ((int64_t)acc[2][rb][v] << 16) + ((int64_t)acc[3][rb][v] << 24);
                 cf = (sc.y & 1) ? (float)(int)tot * ldexpf(1.0f, -sc.x) : __builtin_nanf("");
             }
-            cv[c][v] = cf;
+            cv[v] = cf;
             if (!by_vector) coef[((size_t)g * N + jr) * ST + tv] = cf;
-            if (tv == 0) ell[(size_t)g * N + jr] = l_r;
             if (dbg_samples) {
                 dbg_samples[(size_t)t * N + jr] = l_r;
                 dbg_coef[(size_t)t * N + jr] = cf;
             }
         }
-    }
-    if (by_vector) {
-        // four consecutive draws of one vector per lane: one 16-byte store
-        // (zeros past the batch end, inside the row's padding to JP)
-        const size_t pos = (size_t)kb * JP + jb0 + 4 * (lane >> 4);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int tv = c * 16 + row;
-            if (tv < nx)
-                *reinterpret_cast<f32x4 *>(coef + ((size_t)g * ST + tv) * ((size_t)K * JP) + pos) =
-                    f32x4{cv[c][0], cv[c][1], cv[c][2], cv[c][3]};
+        if (by_vector && col_on) {
+            // four consecutive draws of one vector per lane: one 16-byte store
+            // (zeros past the batch end, inside the row's padding to JP)
+            const size_t pos = (size_t)kb * JP + jb0 + rb * 16 + 4 * (lane >> 4);
+            *reinterpret_cast<f32x4 *>(coef + ((size_t)g * ST + tv) * ((size_t)K * JP) + pos) =
+                f32x4{cv[0], cv[1], cv[2], cv[3]};
         }
     }
 }
@@ -585,7 +614,8 @@ int launch_shared_coef(kerdock_dtype dt, const float *X, int batch, int n, int k
     if (n <= 2048) hipLaunchKernelGGL(k_x_digits<1>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
     else hipLaunchKernelGGL(k_x_digits<2>, dim3(batch), dim3(64), 0, s, X, n, n_pad, digits, xscale);
     KD_LAUNCH("k_x_digits");
-    hipLaunchKernelGGL(k_shared_coef, dim3((unsigned)nb, groups), dim3(256), 0, s, X, n, n_pad, k, L, signs, seed, t0,
+    const size_t sign_lds = (size_t)SC_DRAWS * ((k >= 5 ? (1 << k) / 32 : 1) + 1) * 4;
+    hipLaunchKernelGGL(k_shared_coef, dim3((unsigned)nb, groups), dim3(256), sign_lds, s, X, n, n_pad, k, L, signs, seed, t0,
                        batch, J, K, shared_by_vector(dt) ? 1 : 0, digits, xscale, ell, coef, dbg_samples, dbg_coef);
     KD_LAUNCH("k_shared_coef");
     return KERDOCK_OK;
