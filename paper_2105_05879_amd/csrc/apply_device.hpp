@@ -558,13 +558,18 @@ __device__ __forceinline__ void bucket_coefs(const float *__restrict__ x, int n,
 // LDS of one draws + gather workgroup: the draws, coefficients, direct-sum
 // list and fixed-point x of phase 1, then (aliasing them once phase 2 has
 // read the last pair) the group sums of short columns.
-template <int DT, bool GROUPED, int P> struct DGSmem {
-    static constexpr size_t PHASE1 = 3 * MAX_CHUNK * 4 + (size_t)P * XI_INTS_PER_P * 4 + 16;
+// BK: the kernel can take draws grouped by basis (their list and x in
+// fixed point live in LDS); without it only (l, c) pairs are staged
+template <int DT, bool GROUPED, int P, bool BK = true> struct DGSmem {
+    static constexpr size_t PHASE1 =
+        BK ? 3 * MAX_CHUNK * 4 + (size_t)P * XI_INTS_PER_P * 4 + 16 : 2 * MAX_CHUNK * 4;
     static constexpr size_t RED = GROUPED ? (size_t)GATHER_THREADS * Elems<DT>::N * 4 : 0;
     static constexpr size_t BYTES = PHASE1 > RED ? PHASE1 : RED;
 };
 
-template <int DT, int TILES, int UNROLL, bool GROUPED, int P>
+// BK = false: a kernel that never takes grouped draws (a.bucket must be 0);
+// it leaves out that path and its registers
+template <int DT, int TILES, int UNROLL, bool GROUPED, int P, bool BK = true>
 __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int seg, int nchunks,
                                             unsigned char *smem) {
     uint32_t *s_ell = reinterpret_cast<uint32_t *>(smem);
@@ -590,7 +595,7 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     const int per = ((cnt + 3) / 4 + 3) & ~3;          // the waves' runs of positions
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r0 = min(cnt, wave * per), r1 = min(cnt, r0 + per);
-    if (a.bucket) {
+    if (BK && a.bucket) {
         // the batch's draws grouped by basis (draw_sort), x in fixed point
         // shared through LDS by wave 0, then the four waves' runs
         const uint32_t *src = a.sorted + (size_t)t * N + jbeg;
@@ -623,7 +628,7 @@ __device__ __forceinline__ void draw_gather(const DGArgs &a, int t, int cid, int
     }
     __syncthreads();
     if (dbg_coef && seg == 0) {
-        if (a.bucket) {
+        if (BK && a.bucket) {
             for (int r = threadIdx.x; r < cnt; r += GATHER_THREADS)
                 dbg_coef[(size_t)t * N + a.perm[(size_t)t * N + jbeg + r]] = s_coef[r];
         } else {
@@ -1046,34 +1051,56 @@ __device__ __forceinline__ float dot_finish(const float (&p)[4], const float (&e
 
 // a_i.x by one wave.  Lane l takes the 16-byte pieces l, l + 64, ..., one
 // Dot2 cascade per element position of a piece (or, when rows cannot be read
-// in pieces, elements l, l + 64, ... into one cascade).
+// in pieces, elements l, l + 64, ... into one cascade).  For waves that take
+// many dots in turn (few registers, so more waves hide the loads).
 __device__ __forceinline__ float survivor_dot(const float *__restrict__ row, const float *__restrict__ x,
                                               int n, int vec4) {
     const int lane = threadIdx.x & 63;
     float p[4] = {0.f, 0.f, 0.f, 0.f}, e[4] = {0.f, 0.f, 0.f, 0.f};
     if (vec4) {
-        // n <= 4096: at most 16 pieces per lane, all loaded before the steps
         const float4 *__restrict__ r4 = reinterpret_cast<const float4 *>(row);
         const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
         const int n4 = n >> 2;
-        float4 ra[16], xa[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int q = lane + 64 * i;
-            ra[i] = q < n4 ? r4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-            xa[i] = q < n4 ? x4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (lane + 64 * i < n4) {
-                dot_step(p[0], e[0], ra[i].x, xa[i].x);
-                dot_step(p[1], e[1], ra[i].y, xa[i].y);
-                dot_step(p[2], e[2], ra[i].z, xa[i].z);
-                dot_step(p[3], e[3], ra[i].w, xa[i].w);
-            }
+#pragma unroll 4
+        for (int q = lane; q < n4; q += 64) {
+            const float4 a = r4[q], b = x4[q];
+            dot_step(p[0], e[0], a.x, b.x);
+            dot_step(p[1], e[1], a.y, b.y);
+            dot_step(p[2], e[2], a.z, b.z);
+            dot_step(p[3], e[3], a.w, b.w);
         }
     } else {
         for (int q = lane; q < n; q += 64) dot_step(p[0], e[0], row[q], x[q]);
+    }
+    return dot_finish(p, e);
+}
+
+// The same dot with all pieces of the row and of x loaded before the steps
+// (n <= 4096: at most 16 pieces per lane), for a wave that takes one dot:
+// one round of loads instead of four.  Same steps in the same order.
+__device__ __forceinline__ float survivor_dot_once(const float *__restrict__ row, const float *__restrict__ x,
+                                                   int n, int vec4) {
+    const int lane = threadIdx.x & 63;
+    if (!vec4) return survivor_dot(row, x, n, vec4);
+    float p[4] = {0.f, 0.f, 0.f, 0.f}, e[4] = {0.f, 0.f, 0.f, 0.f};
+    const float4 *__restrict__ r4 = reinterpret_cast<const float4 *>(row);
+    const float4 *__restrict__ x4 = reinterpret_cast<const float4 *>(x);
+    const int n4 = n >> 2;
+    float4 ra[16], xa[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int q = lane + 64 * i;
+        ra[i] = q < n4 ? r4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        xa[i] = q < n4 ? x4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (lane + 64 * i < n4) {
+            dot_step(p[0], e[0], ra[i].x, xa[i].x);
+            dot_step(p[1], e[1], ra[i].y, xa[i].y);
+            dot_step(p[2], e[2], ra[i].z, xa[i].z);
+            dot_step(p[3], e[3], ra[i].w, xa[i].w);
+        }
     }
     return dot_finish(p, e);
 }
@@ -1163,8 +1190,8 @@ __device__ __forceinline__ void survivors_vec(const SurvArgs &a, int t, float *v
 __device__ __forceinline__ void survivor_dots_split(const SurvArgs &a, int t, int s) {
     if (a.active && !a.active[t]) return;
     if (s >= min(a.nsurv[t], a.s_max)) return;
-    const float v = survivor_dot(a.A + (size_t)a.surv[(size_t)t * a.s_max + s] * a.n,
-                                 a.X + (size_t)t * a.n, a.n, a.vec4);
+    const float v = survivor_dot_once(a.A + (size_t)a.surv[(size_t)t * a.s_max + s] * a.n,
+                                      a.X + (size_t)t * a.n, a.n, a.vec4);
     if ((threadIdx.x & 63) == 0) a.svals[(size_t)t * a.s_max + s] = v;
 }
 

@@ -66,12 +66,13 @@ __global__ void k_multi_end(int64_t *t0, const int *batch, int nh) {
     if (q < nh) t0[q] += batch[q];
 }
 
-template <int DT, int TILES, int UNROLL, int P>
+template <int DT, int TILES, int UNROLL, int P, bool BK>
 __global__ __launch_bounds__(GATHER_THREADS) void k_multi_draw_gather(
     const DGArgs *__restrict__ hd, const int *__restrict__ nchunks, const int *__restrict__ grouped,
     const uint64_t *__restrict__ items, int nitems, int *counter) {
-    constexpr size_t SMEM = DGSmem<DT, true, P>::BYTES > DGSmem<DT, false, P>::BYTES ? DGSmem<DT, true, P>::BYTES
-                                                                                     : DGSmem<DT, false, P>::BYTES;
+    constexpr size_t SMEM = DGSmem<DT, true, P, BK>::BYTES > DGSmem<DT, false, P, BK>::BYTES
+                                ? DGSmem<DT, true, P, BK>::BYTES
+                                : DGSmem<DT, false, P, BK>::BYTES;
     __shared__ __align__(16) unsigned char smem[SMEM];
     __shared__ int s_item;
     for (;;) {
@@ -84,9 +85,9 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_multi_draw_gather(
         unpack_item(items[it], q, seg, cid, t);
         const DGArgs &a = hd[q];
         if (grouped[q])
-            draw_gather<DT, TILES, UNROLL, true, P>(a, t, cid, seg, nchunks[q], smem);
+            draw_gather<DT, TILES, UNROLL, true, P, BK>(a, t, cid, seg, nchunks[q], smem);
         else
-            draw_gather<DT, TILES, UNROLL, false, P>(a, t, cid, seg, nchunks[q], smem);
+            draw_gather<DT, TILES, UNROLL, false, P, BK>(a, t, cid, seg, nchunks[q], smem);
     }
 }
 
@@ -132,6 +133,7 @@ struct kerdock_multi_s {
     int batch[kd::MAX_MULTI] = {}, K[kd::MAX_MULTI] = {}, s_max[kd::MAX_MULTI] = {};
     int m[kd::MAX_MULTI] = {};
     int tiles = 1, P = 1, kmax = 1, unroll = 8;
+    int any_bucket = 0;               // some handle groups its draws by basis
     int nitems = 0, total_batch = 0, max_m = 1, max_smax = 1, grid = 0;
     kd::MultiSelect msel{};
     kd::MultiSurv msurv{};
@@ -159,24 +161,30 @@ size_t sort_lds_bytes(int k);
 
 static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
 
-template <int DT, int TILES, int U, int P>
+template <int DT, int TILES, int U, int P, bool BK>
 static void multi_launch_dt(const kerdock_multi_s *pl, hipStream_t s) {
-    hipLaunchKernelGGL((k_multi_draw_gather<DT, TILES, U, P>), dim3(pl->grid), dim3(GATHER_THREADS), 0, s,
+    hipLaunchKernelGGL((k_multi_draw_gather<DT, TILES, U, P, BK>), dim3(pl->grid), dim3(GATHER_THREADS), 0, s,
                        pl->dg_dev, pl->nchunks_dev, pl->grouped_dev, pl->items, pl->nitems, pl->counter);
 }
 
+// Plans without a handle that groups its draws run kernels without that path
+// (fewer registers, more resident workgroups) at the tuned unroll; plans with
+// one use a single unroll per tile count (the unroll never changes results).
 template <int DT, int TILES, int P>
 static void multi_launch_u(const kerdock_multi_s *pl, hipStream_t s) {
-    if (TILES == 4) {
-        if (pl->unroll <= 2) multi_launch_dt<DT, TILES, 2, P>(pl, s);
-        else multi_launch_dt<DT, TILES, 4, P>(pl, s);
-    } else if (TILES == 2) {
-        if (pl->unroll <= 4) multi_launch_dt<DT, TILES, 4, P>(pl, s);
-        else multi_launch_dt<DT, TILES, 8, P>(pl, s);
+    if constexpr (TILES == 4) {
+        if (pl->any_bucket) multi_launch_dt<DT, TILES, 4, P, true>(pl, s);
+        else if (pl->unroll <= 2) multi_launch_dt<DT, TILES, 2, P, false>(pl, s);
+        else multi_launch_dt<DT, TILES, 4, P, false>(pl, s);
+    } else if constexpr (TILES == 2) {
+        if (pl->any_bucket) multi_launch_dt<DT, TILES, 8, P, true>(pl, s);
+        else if (pl->unroll <= 4) multi_launch_dt<DT, TILES, 4, P, false>(pl, s);
+        else multi_launch_dt<DT, TILES, 8, P, false>(pl, s);
     } else {
-        if (pl->unroll <= 4) multi_launch_dt<DT, TILES, 4, P>(pl, s);
-        else if (pl->unroll >= 16) multi_launch_dt<DT, TILES, 16, P>(pl, s);
-        else multi_launch_dt<DT, TILES, 8, P>(pl, s);
+        if (pl->any_bucket) multi_launch_dt<DT, TILES, 8, P, true>(pl, s);
+        else if (pl->unroll <= 4) multi_launch_dt<DT, TILES, 4, P, false>(pl, s);
+        else if (pl->unroll >= 16) multi_launch_dt<DT, TILES, 16, P, false>(pl, s);
+        else multi_launch_dt<DT, TILES, 8, P, false>(pl, s);
     }
 }
 
@@ -202,33 +210,46 @@ static void multi_gather(const kerdock_multi_s *pl, hipStream_t s) {
 }
 
 // persistent grid: workgroups resident at once on the device
-template <int DT, int TILES, int U, int P>
+template <int DT, int TILES, int U, int P, bool BK>
 static int resident_dt(int cus) {
     int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_multi_draw_gather<DT, TILES, U, P>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_multi_draw_gather<DT, TILES, U, P, BK>,
                                                      GATHER_THREADS, 0) != hipSuccess || per < 1)
         per = 1;
     return per * cus;
 }
 
+// occupancy of the instantiation that multi_gather would launch
+template <int DT, int TILES, int P>
+static int resident_u(const kerdock_multi_s *pl, int cus) {
+    if constexpr (TILES == 4) {
+        if (pl->any_bucket) return resident_dt<DT, TILES, 4, P, true>(cus);
+        return pl->unroll <= 2 ? resident_dt<DT, TILES, 2, P, false>(cus) : resident_dt<DT, TILES, 4, P, false>(cus);
+    } else if constexpr (TILES == 2) {
+        if (pl->any_bucket) return resident_dt<DT, TILES, 8, P, true>(cus);
+        return pl->unroll <= 4 ? resident_dt<DT, TILES, 4, P, false>(cus) : resident_dt<DT, TILES, 8, P, false>(cus);
+    } else {
+        if (pl->any_bucket) return resident_dt<DT, TILES, 8, P, true>(cus);
+        return pl->unroll <= 4    ? resident_dt<DT, TILES, 4, P, false>(cus)
+               : pl->unroll >= 16 ? resident_dt<DT, TILES, 16, P, false>(cus)
+                                  : resident_dt<DT, TILES, 8, P, false>(cus);
+    }
+}
+
+template <int DT, int P>
+static int resident_t(const kerdock_multi_s *pl, int cus) {
+    if (pl->tiles == 1) return resident_u<DT, 1, P>(pl, cus);
+    if (pl->tiles == 2) return resident_u<DT, 2, P>(pl, cus);
+    return resident_u<DT, 4, P>(pl, cus);
+}
+
 static int resident(const kerdock_multi_s *pl, int cus) {
-    // occupancy of the instantiation that multi_gather would launch
-#define KD_RES(DT)                                                                                 \
-    if (pl->P == 1) {                                                                              \
-        if (pl->tiles == 1) return pl->unroll <= 4 ? resident_dt<DT, 1, 4, 1>(cus) : pl->unroll >= 16 ? resident_dt<DT, 1, 16, 1>(cus) : resident_dt<DT, 1, 8, 1>(cus); \
-        if (pl->tiles == 2) return pl->unroll <= 4 ? resident_dt<DT, 2, 4, 1>(cus) : resident_dt<DT, 2, 8, 1>(cus); \
-        return pl->unroll <= 2 ? resident_dt<DT, 4, 2, 1>(cus) : resident_dt<DT, 4, 4, 1>(cus);    \
-    } else {                                                                                       \
-        if (pl->tiles == 1) return pl->unroll <= 4 ? resident_dt<DT, 1, 4, 2>(cus) : pl->unroll >= 16 ? resident_dt<DT, 1, 16, 2>(cus) : resident_dt<DT, 1, 8, 2>(cus); \
-        if (pl->tiles == 2) return pl->unroll <= 4 ? resident_dt<DT, 2, 4, 2>(cus) : resident_dt<DT, 2, 8, 2>(cus); \
-        return pl->unroll <= 2 ? resident_dt<DT, 4, 2, 2>(cus) : resident_dt<DT, 4, 4, 2>(cus);    \
-    }
     switch (pl->dtype) {
-    case KERDOCK_F32: KD_RES(KERDOCK_F32)
-    case KERDOCK_BF16: KD_RES(KERDOCK_BF16)
-    case KERDOCK_FP8E4M3: KD_RES(KERDOCK_FP8E4M3)
+    case KERDOCK_F32: return pl->P == 1 ? resident_t<KERDOCK_F32, 1>(pl, cus) : resident_t<KERDOCK_F32, 2>(pl, cus);
+    case KERDOCK_BF16: return pl->P == 1 ? resident_t<KERDOCK_BF16, 1>(pl, cus) : resident_t<KERDOCK_BF16, 2>(pl, cus);
+    case KERDOCK_FP8E4M3:
+        return pl->P == 1 ? resident_t<KERDOCK_FP8E4M3, 1>(pl, cus) : resident_t<KERDOCK_FP8E4M3, 2>(pl, cus);
     }
-#undef KD_RES
     return cus;
 }
 
@@ -338,6 +359,7 @@ int kerdock_multi_create(const kerdock_handle *hs, int nh, const float *const *X
         pl->m[q] = h->m;
         off_partial[q] = off; off += al((size_t)batch[q] * nchunks[q] * h->pitch * 4);
         bucket[q] = use_bucket(h, J);
+        pl->any_bucket |= bucket[q];
         off_jlist[q] = off; off += bucket[q] ? al((size_t)batch[q] * J * K * 4) : 0;
         off_sorted[q] = off; off += bucket[q] ? al((size_t)batch[q] * J * K * 4) : 0;
         pl->msort.offset[q] = pl->sort_wgs;
