@@ -52,8 +52,10 @@ def test_signs_and_field_bit_exact(orc, n):
 
 # --------------------------------------------------------------- tables ---
 
+# (130, 257) and (33, 4095): d = 1024 and 4096 with n not a multiple of 4 (rows read element by
+# element) and a partial last segment of a lane
 TABLE_CASES = [(1, 1), (3, 4), (16, 16), (50, 50), (64, 64), (100, 100), (300, 100), (70, 300),
-               (256, 256), (1000, 1000), (2048, 2048)]
+               (256, 256), (130, 257), (1000, 1000), (2048, 2048), (33, 4095)]
 
 
 def pick_columns(L, d, n, count, seed):
