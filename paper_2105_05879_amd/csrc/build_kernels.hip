@@ -260,10 +260,9 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
 
 // ------------------------------------------------- table build, d >= 256 --
 // The same transform with fewer vector instructions, in workgroups of ROWS
-// waves (two or more workgroups per CU, so that one's loads and stores
-// overlap another's arithmetic).  Wave r holds row i0 + r; lane l holds the
-// R = d/64 consecutive input elements x = (l ^ 15) R + q in registers q < R
-// (16-byte loads), r = log2 R, so that
+// waves.  Wave r holds row i0 + r; lane l holds R = d/64 consecutive input
+// elements of the row in registers q < R (16-byte loads), r = log2 R.  For
+// d = 256 (R = 4, fwht_wave2) lane l holds x = (l ^ 15) R + q, so that
 //   * x bits 0..r-1 (the register index): butterflies inside each lane;
 //   * x bits r..r+3 (lane bits 0..3, xor 1, 2, 4, 8): the partner value
 //     arrives by DPP (quad_perm, row_half_mirror + quad_perm, row_ror:8) and
@@ -274,16 +273,17 @@ __global__ __launch_bounds__(BuildShape<DT>::THREADS) void k_table_build(
 //     cancels exactly, H[w][x ^ M] = (-1)^{w . M} H[w][x];
 //   * x bits r+4, r+5 (lane bits 4, 5): v_permlane16_swap / permlane32_swap
 //     exchange lane bit 4 (5) with register bit 0 (1), after which the pair
-//     sits in one lane and the butterfly is local.
-// Output w of register q in lane l:
+//     sits in one lane and the butterfly is local;
+// output w of register q in lane l:
 //   w = (l >> 4 & 1) | (l >> 5 & 1) << 1 | (q & (R - 4)) | (l & 15) << r |
 //       (q & 3) << (r + 4),
-// so for d = 4096 a chunk of 1024 columns is one value of q & 3.  Staging is
-// [row][slot] with slot = w' ^ ((w' >> 6 & 15) << 2), w' = w mod 1024 (the 64
-// lanes of a write and the 32 columns of a read hit distinct banks), row
-// pitch 1032 floats; each thread then stores 4 consecutive rows of a column
-// (16, 8 or 4 bytes).  The barriers around the staging wait for LDS only:
-// stores to the table need not complete before the next chunk.
+// staged with slot = w' ^ ((w' >> 6 & 15) << 2), w' = w mod 1024, row pitch
+// 1032 floats.  For d >= 1024 (R >= 16, fwht_wave3 below) the four lane bits
+// go through LDS into registers instead, with the output map and staging
+// given there.  For d = 4096 a chunk of 1024 columns is one value of q & 3.
+// Each thread then stores PACK consecutive rows of a column (4 to 16 bytes).
+// The barriers around the staging wait for LDS only: stores to the table
+// need not complete before the next chunk.
 constexpr int STAGE2_PITCH = 1032;
 
 __device__ __forceinline__ void lds_barrier() {
@@ -357,6 +357,85 @@ template <int DT, int PACK> __device__ __forceinline__ void store_rows(unsigned 
     else *reinterpret_cast<uint4 *>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// R >= 16 (d >= 1024): the same transform with lane bits 0..3 moved into
+// registers instead of crossed by DPP.  Lane l holds x = l R + q (natural
+// order).  After the register levels (x bits 0..r-1), each group of 16
+// registers (register bits 4.. fixed) is transposed through this wave's LDS
+// region tr (1088 floats: [lane bits 4,5][register bit 0..3][17-float row],
+// conflict-free writes and reads), which exchanges lane bits 0..3 with
+// register bits 0..3: lane l' then holds x bits 0..3 in its bits 0..3 and
+// registers q' hold x bits r..r+3 in their bits 0..3, so those four levels
+// are in-register butterflies (one instruction per element instead of a DPP
+// move and an FMA).  Lane bits 4, 5 (x bits r+4, r+5) as in fwht_wave2.
+// Output w of register q' in lane l':
+//   w = (l' & 15) | (q' & (R - 16)) | (l' >> 4 & 3) << r | (q' >> 2 & 3) << (r + 2) |
+//       (q' & 1) << (r + 4) | (q' >> 1 & 1) << (r + 5),
+// staged with slot = w' ^ ((w' >> 6 & 3) << 4), w' = w mod 1024 (a write's 64
+// lanes meet 64 banks), row pitch 1024 + 64 / ROWS floats (a read's row
+// groups, PACK rows apart, start 64 / TPC banks apart).
+constexpr int TR_WAVE = 1088;                  // floats of a wave's transpose region
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int LOGD> __device__ __forceinline__ void fwht_wave3(float *v, float *tr) {
+    constexpr int R = (1 << LOGD) / 64;
+    static_assert(R >= 16, "four register bits to exchange");
+    const int lane = threadIdx.x & 63, l_hi = lane >> 4, l_lo = lane & 15;
+    // register bits
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (q & h) continue;
+            const float a = v[q], b = v[q + h];
+            v[q] = a + b;
+            v[q + h] = a - b;
+        }
+    // lane bits 0..3 <-> register bits 0..3, 16 registers at a time
+#pragma unroll
+    for (int c = 0; c < R / 16; ++c) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) tr[(l_hi * 16 + j) * 17 + l_lo] = v[c * 16 + j];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[c * 16 + i] = tr[(l_hi * 16 + l_lo) * 17 + i];
+        wave_lds_sync();                       // before the next group overwrites the region
+    }
+    // the exchanged bits, now register bits 0..3
+#pragma unroll
+    for (int h = 1; h < 16; h <<= 1)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (q & h) continue;
+            const float a = v[q], b = v[q + h];
+            v[q] = a + b;
+            v[q + h] = a - b;
+        }
+    // lane bit 4 <-> register bit 0, then the butterfly in the lane
+#pragma unroll
+    for (int q = 0; q < R; q += 2) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[q]), __float_as_uint(v[q + 1]), false,
+                                                        false);
+        const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
+        v[q] = a + b;
+        v[q + 1] = a - b;
+    }
+    // lane bit 5 <-> register bit 1
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (q & 2) continue;
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[q]), __float_as_uint(v[q + 2]), false,
+                                                        false);
+        const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
+        v[q] = a + b;
+        v[q + 2] = a - b;
+    }
+}
+
 template <int LOGD, int DT, int ROWS, int PACK>
 __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restrict__ A, int m, int n, int pitch,
                                                               const uint32_t *__restrict__ signs,
@@ -368,7 +447,12 @@ __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restr
     constexpr int COLS = D < STAGE_COLS ? D : STAGE_COLS;
     constexpr int QC = COLS / 64;                       // registers per chunk
     constexpr int THREADS = ROWS * 64;
-    __shared__ __align__(16) float stage[ROWS * STAGE2_PITCH];
+    constexpr bool TR = R >= 16;                        // lane bits 0..3 through LDS (fwht_wave3)
+    // staging row pitch: a read's row groups (PACK rows apart) start 64 / TPC
+    // banks apart, so they meet distinct banks (PACK (64 / ROWS) = 64 / TPC)
+    constexpr int PITCH = TR ? 1024 + 64 / ROWS : STAGE2_PITCH;
+    constexpr int LDS_ROW = TR && TR_WAVE > PITCH ? TR_WAVE : PITCH;
+    __shared__ __align__(16) float stage[ROWS * LDS_ROW];
 
     int g = blockIdx.x, b, strip;
     if (xcd_map) {
@@ -383,7 +467,7 @@ __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restr
     const int i0 = strip * ROWS;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = i0 + wave;
-    const int seg = lane ^ 15;                          // input segment of this lane
+    const int seg = TR ? lane : lane ^ 15;              // input segment of this lane
     const int x0 = seg * R;
 
     // signed, zero-padded row: 64 (R) consecutive elements per lane
@@ -416,7 +500,12 @@ __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restr
         for (int q = 0; q < R; ++q)
             v[q] = __uint_as_float(__float_as_uint(v[q]) ^ (((sw[q >> 5] >> (q & 31)) & 1u) << 31));
     }
-    fwht_wave2<LOGD>(v);
+    if constexpr (TR) {
+        fwht_wave3<LOGD>(v, stage + wave * TR_WAVE);
+        lds_barrier();                                  // every wave done with its transpose region
+    } else {
+        fwht_wave2<LOGD>(v);
+    }
 
     constexpr int TPC = ROWS / PACK;                   // threads per column
     constexpr int CPP = THREADS / TPC;                  // columns per pass
@@ -429,7 +518,11 @@ __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restr
     const size_t col_bytes = (size_t)pitch * BT;
     // output index of register q in this lane, less its register bits
     constexpr int LR = LOGD - 6;
-    const int w_lane = ((lane >> 4) & 1) | ((lane >> 5) & 1) << 1 | (lane & 15) << LR;
+    const int w_lane = TR ? (lane & 15) | ((lane >> 4) & 3) << LR
+                          : ((lane >> 4) & 1) | ((lane >> 5) & 1) << 1 | (lane & 15) << LR;
+    // staging slot of column wl (mod COLS): the 64 lanes of a write and the
+    // columns of a read meet distinct banks
+    auto slot_of = [](int wl) { return TR ? wl ^ (((wl >> 6) & 3) << 4) : wl ^ (((wl >> 6) & 15) << 2); };
 
 #pragma unroll
     for (int c = 0; c < R / QC; ++c) {
@@ -437,19 +530,18 @@ __global__ __launch_bounds__(ROWS * 64) void k_table_build2(const float *__restr
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             if ((((q & 3) << (LR + 4)) >> 10) != c) continue;   // w >> 10, as w_lane < 1024
-            const int w = w_lane | (q & (R - 4)) | (q & 3) << (LR + 4);
-            const int wl = w & (COLS - 1);
-            const int slot = wl ^ (((wl >> 6) & 15) << 2);
-            stage[wave * STAGE2_PITCH + slot] = v[q];
+            const int w = TR ? w_lane | (q & (R - 16)) | ((q >> 2) & 3) << (LR + 2) | (q & 3) << (LR + 4)
+                             : w_lane | (q & (R - 4)) | (q & 3) << (LR + 4);
+            stage[wave * PITCH + slot_of(w & (COLS - 1))] = v[q];
         }
         lds_barrier();
         const size_t colbase = (size_t)b * D + (size_t)c * COLS;
         for (int cc = threadIdx.x / TPC; cc < COLS; cc += CPP) {
-            const int slot = cc ^ (((cc >> 6) & 15) << 2);
+            const int slot = slot_of(cc);
             float vals[PACK];
 #pragma unroll
             for (int r = 0; r < PACK; ++r) {
-                const float t = stage[(my_rows + r) * STAGE2_PITCH + slot];
+                const float t = stage[(my_rows + r) * PITCH + slot];
                 vals[r] = DT == KERDOCK_FP8E4M3 ? t * inv_scale[r] : t;
             }
             unsigned char *dst = out + (colbase + cc) * col_bytes + (size_t)(i0 + my_rows) * BT;
@@ -547,13 +639,14 @@ int launch_row_scales(const float *A, int m, int n, int pitch, int d, kerdock_dt
 // rows per workgroup and rows per store of k_table_build2.  The write rate
 // follows the length of the column segment one workgroup writes (measured
 // on the n = 2048, m = 2048 tables: 32-byte segments about 1.9 TB/s, 64-byte
-// segments about 3.3 TB/s), so FP32 takes 16 rows (one workgroup per CU at
-// its register count); BF16 measured the same with 8 or 16 rows (19 ms) and
-// FP8 is bound by its conversions, where 8-row workgroups (two or more per
-// CU) overlap one's stores with another's arithmetic.
+// segments about 3.4 TB/s), so FP32 and BF16 take 16 rows (one or two
+// workgroups per CU at their register count; BF16 17.2 ms with 16 rows
+// against 19.5 ms with 8); FP8 is bound by its vector work, where 8-row
+// workgroups (several per CU) overlap one's stores with another's
+// arithmetic (15.6 ms against 16.6 ms with 16 rows).
 template <int DT> struct Build2Shape {
-    static constexpr int ROWS = DT == KERDOCK_F32 ? 16 : 8;
-    static constexpr int PACK = DT == KERDOCK_BF16 ? 4 : DT == KERDOCK_F32 ? 4 : 8;
+    static constexpr int ROWS = DT == KERDOCK_FP8E4M3 ? 8 : 16;
+    static constexpr int PACK = DT == KERDOCK_F32 ? 4 : 8;
 };
 
 template <int LOGD, int DT, int ROWS, int PACK>
