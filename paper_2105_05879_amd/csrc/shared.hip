@@ -435,7 +435,7 @@ __device__ __forceinline__ void split3x2(float c0, float c1, uint32_t p[3]) {
 // Wave w owns rows 128 (w % 2) .. + 127 and vectors 32 (w / 2) .. + 31: 8 x 2
 // MFMA blocks, 3 MFMAs (one per part) per block and 32 draws.
 template <int DT>
-__global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__restrict__ table, int col_bytes,
+__global__ __launch_bounds__(256, 2) void k_shared_gemm16(const unsigned char *__restrict__ table, int col_bytes,
                                                        int pitch, int batch, int J, int K, int N, int splits,
                                                        const uint32_t *__restrict__ ell,
                                                        const float *__restrict__ coef,
@@ -467,20 +467,22 @@ __global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__re
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // The loads are branch-free (indices clamped into the slice, values
-    // masked), so that all of a stage's loads are in flight together; the
-    // draw indices are loaded one stage ahead of the table entries they
-    // address.
+    // masked), so that all of a stage's loads are in flight together.  Two
+    // stages of table entries are in flight (register sets 0 and 1, taken in
+    // turn), and the draw indices of stage s are loaded before the table
+    // entries of stage s - 1: vector loads complete in order, so waiting for
+    // the indices never waits for table entries still in flight.
     const int Jq = (Jl - 1) & ~3;                  // last aligned quad of the slice
     const float *__restrict__ cfr = bt_ok ? cf : coef + ((size_t)g * ST) * ((size_t)K * JP) + (size_t)kb * JP + js;
     const size_t aoff = (size_t)(arow_ok ? arow : 0) * EB;
-    uint32_t lv[8];
-    uint32_t ra[8][LW];
-    f32x4 rb[4];
-    auto fetch_ell = [&](int j0) {
+    uint32_t lv0[8], lv1[8];
+    uint32_t ra0[8][LW], ra1[8][LW];
+    f32x4 rb0[4], rb1[4];
+    auto fetch_ell = [&](uint32_t (&lv)[8], int j0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) lv[e] = el[min(j0 + 8 * ad + e, Jl - 1)];
     };
-    auto fetch = [&](int j0) {
+    auto fetch = [&](uint32_t (&ra)[8][LW], f32x4 (&rb)[4], const uint32_t (&lv)[8], int j0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const unsigned char *src = table + (size_t)lv[e] * (size_t)col_bytes + aoff;
@@ -496,11 +498,8 @@ __global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__re
         for (int u = 0; u < 4; ++u)
             rb[u] = *reinterpret_cast<const f32x4 *>(cfr + min(j0 + 16 * bq + 4 * u, Jq));
     };
-
-    fetch_ell(0);
-    fetch(0);
-    fetch_ell(SB_BK);
-    for (int j0 = 0; j0 < Jl; j0 += SB_BK) {
+    // one stage's operands into LDS
+    auto stage = [&](const uint32_t (&ra)[8][LW], const f32x4 (&rb)[4], int j0) {
         {
             // rows as packed BF16 pairs: q[e][w] holds rows 2w, 2w + 1 of draw e
             // (values past the slice end or the last row are masked here,
@@ -555,11 +554,8 @@ __global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__re
                     *reinterpret_cast<u32x4 *>(&Bs[part][bt][16 * bq + 8 * h]) =
                         u32x4{p[2 * h][0][part], p[2 * h][1][part], p[2 * h + 1][0][part], p[2 * h + 1][1][part]};
         }
-        __syncthreads();
-        if (j0 + SB_BK < Jl) {
-            fetch(j0 + SB_BK);
-            fetch_ell(j0 + 2 * SB_BK);
-        }
+    };
+    auto mma = [&]() {
 #pragma unroll
         for (int kk = 0; kk < SB_BK; kk += 32) {
             const int kc = kk + 8 * (lane >> 4);
@@ -577,7 +573,43 @@ __global__ __launch_bounds__(256) void k_shared_gemm16(const unsigned char *__re
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb, acc[a][b], 0, 0, 0);
                 }
         }
+    };
+
+    // (the scheduling barriers keep the loads in this issue order)
+    fetch_ell(lv0, 0);
+    fetch_ell(lv1, SB_BK);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(ra0, rb0, lv0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch_ell(lv0, 2 * SB_BK);
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(ra1, rb1, lv1, SB_BK);
+    __builtin_amdgcn_sched_barrier(0);
+    // pairs of stages, then a last single one (the loads past the slice end
+    // are clamped into it and never used)
+    int j0 = 0;
+    for (; j0 + SB_BK < Jl; j0 += 2 * SB_BK) {
+        stage(ra0, rb0, j0);
         __syncthreads();
+        fetch_ell(lv1, j0 + 3 * SB_BK);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(ra0, rb0, lv0, j0 + 2 * SB_BK);
+        __builtin_amdgcn_sched_barrier(0);
+        mma();
+        __syncthreads();
+        stage(ra1, rb1, j0 + SB_BK);
+        __syncthreads();
+        fetch_ell(lv0, j0 + 4 * SB_BK);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(ra1, rb1, lv1, j0 + 3 * SB_BK);
+        __builtin_amdgcn_sched_barrier(0);
+        mma();
+        __syncthreads();
+    }
+    if (j0 < Jl) {
+        stage(ra0, rb0, j0);
+        __syncthreads();
+        mma();
     }
     // D block (a, b): lane holds rows 4 (lane / 16) + v, v < 4, of column lane % 16
 #pragma unroll
