@@ -23,7 +23,8 @@ SHARED_CASES = [
     (100, 100, 70, 50, 3, 20),
     (300, 100, 130, 37, 2, 40),
     (70, 300, 65, 64, 1, 30),
-    (1000, 1000, 64, 130, 2, 60),
+    (1000, 1000, 64, 130, 2, 60),        # three 64-draw stages: a pair and a last single one
+    (80, 120, 64, 100, 2, 24),           # two stages: one pair, no single last stage
     (64, 64, 70, 4099, 1, 16),          # two slices, the second with a ragged end
     (40, 100, 65, 4101, 2, 12),         # two batches of two ragged slices each
     (50, 50, 66, 21, 5, 10),            # five batches: median of five means
