@@ -25,6 +25,10 @@ SHARED_CASES = [
     (70, 300, 65, 64, 1, 30),
     (1000, 1000, 64, 130, 2, 60),        # three 64-draw stages: a pair and a last single one
     (80, 120, 64, 100, 2, 24),           # two stages: one pair, no single last stage
+    (128, 64, 3, 65, 1, 8),              # a pair whose second stage holds one draw
+    (200, 64, 1, 128, 3, 16),            # one vector; exactly one pair per batch
+    (300, 256, 65, 192, 1, 32),          # a pair and a full last single stage
+    (64, 128, 130, 257, 2, 24),          # two pairs and a one-draw last stage, ragged group
     (64, 64, 70, 4099, 1, 16),          # two slices, the second with a ragged end
     (40, 100, 65, 4101, 2, 12),         # two batches of two ragged slices each
     (50, 50, 66, 21, 5, 10),            # five batches: median of five means
