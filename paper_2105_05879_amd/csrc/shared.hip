@@ -52,14 +52,23 @@ constexpr int SG_BK = 32;                     // draws per LDS stage
 // so c = (sum_b 256^b C_b) 2^-E2 equals the per-vector form's exact signed sum.
 // Identity draws (basis d/2) give sqrt(d) x[w] directly.
 
+// Workgroups are dealt to the 8 XCDs in turn by id; this numbering gives each
+// XCD one contiguous range of [0, total) instead, taken in order.
+__device__ __forceinline__ int xcd_contiguous(int id, int total) {
+    const int q = total / 8, r = total % 8, x = id % 8;
+    return x * q + min(x, r) + id / 8;
+}
+
 // k_x_digits: grid (batch), one wave.  The digits of x_t at digit_offset
 // (coordinates q < n_pad, zero beyond n) and xscale[t] = (scale exponent,
 // flags): bit 0 x_t is finite, bit 1 its top digit plane (b = 3) has a
-// nonzero digit.
+// nonzero digit.  Vectors are numbered contiguously per XCD: the 16 vectors
+// whose 16-byte pieces share a 256-byte digit block then write through one
+// L2, where the pieces merge into whole lines.
 template <int P>
 __global__ __launch_bounds__(64) void k_x_digits(const float *__restrict__ X, int n, int n_pad,
                                                  int8_t *__restrict__ digits, int2 *__restrict__ xscale) {
-    const int t = blockIdx.x, lane = threadIdx.x;
+    const int t = xcd_contiguous(blockIdx.x, gridDim.x), lane = threadIdx.x;
     int xi[P][32];
     int E2;
     bool finite;
