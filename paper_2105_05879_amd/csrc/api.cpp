@@ -78,8 +78,10 @@ int chunk_for(const kerdock_handle_s *h, int J, int requested) {
     return c < J ? c : J;
 }
 
-static int gather_unroll(const kerdock_handle_s *h) {
-    return env_int("KERDOCK_UNROLL", h->tune_unroll > 0 ? h->tune_unroll : 8);
+// Draws in flight per thread: 16 for short columns (several per workgroup
+// step, e.g. 2 KiB FP8 columns: 15.0 -> 14.8 ms at n = m = 2048), 8 otherwise.
+static int gather_unroll(const kerdock_handle_s *h, bool grouped) {
+    return env_int("KERDOCK_UNROLL", h->tune_unroll > 0 ? h->tune_unroll : grouped ? 16 : 8);
 }
 
 // Whether a call groups its draws by basis before the gather (draw_sort and
@@ -264,10 +266,12 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
     dg.J = J;
     dg.chunk = chunk;
     dg.chunks_per_batch = cpb;
+    bool grouped;
     {
         const GatherShape gs = gather_shape(h->dtype, h->pitch);
         dg.groups = gs.groups;
         dg.tpc = gs.tpc;
+        grouped = gs.grouped != 0;
     }
     dg.pitch = h->pitch;
     dg.partial = partial;
@@ -286,7 +290,7 @@ static int apply_ws(kerdock_handle h, const float *X, int batch, float eps, int 
                 svals, surv_vec4(X, h->n), h->m, row_ws};
     if (dg.bucket) rc = launch_draw_sort(dg, batch, K, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[1], s));
-    if (rc == KERDOCK_OK) rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h), s);
+    if (rc == KERDOCK_OK) rc = launch_draw_gather(h->dtype, dg, batch, K, gather_unroll(h, grouped), s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[2], s));
     if (rc == KERDOCK_OK) rc = launch_select(sa, batch, s);
     if (timed && rc == KERDOCK_OK) KD_HIP(hipEventRecord(h->ev[3], s));
@@ -352,7 +356,7 @@ int kerdock_autotune(kerdock_handle h, const float *X, int batch, int J, int K, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const GatherShape gs = gather_shape(h->dtype, h->pitch);
     std::vector<int> unrolls;
-    if (gs.grouped) unrolls = {4, 8};
+    if (gs.grouped) unrolls = {4, 8, 16};
     else if (gs.tiles == 1) unrolls = {4, 8, 16};
     else if (gs.tiles == 2) unrolls = {4, 8};
     else unrolls = {2, 4};

@@ -194,6 +194,7 @@ template <int DT>
 static void launch_dt(dim3 grid, const GatherShape &g, int unroll, const DGArgs &a, hipStream_t s) {
     if (g.grouped) {
         if (unroll <= 4) launch_dg<DT, 1, 4, true>(grid, a, s);
+        else if (unroll >= 16) launch_dg<DT, 1, 16, true>(grid, a, s);
         else launch_dg<DT, 1, 8, true>(grid, a, s);
     } else if (g.tiles == 1) {
         if (unroll <= 4) launch_dg<DT, 1, 4, false>(grid, a, s);
